@@ -1,0 +1,70 @@
+"""FITS-WCS pixel -> world for the oracle (test infrastructure).
+
+Written from the FITS WCS papers cited in the paper's introduction
+(Greisen & Calabretta 2002; Calabretta & Greisen 2002), for the two
+projections the benchmark grids use:
+
+* CAR, non-oblique (CRVAL2 = 0): the plate carree, lon = CRVAL1 + x,
+  lat = y with intermediate coordinates x = CDELT1 (i - CRPIX1),
+  y = CDELT2 (j - CRPIX2); a field away from the equator is placed with
+  CRPIX2.  An oblique CAR (CRVAL2 != 0) is not supported (reading of the
+  paper: it says any WCS projection is supported; the benchmark grids need
+  only this form).
+* SIN (orthographic zenithal, LONPOLE = 180 deg): R = sqrt(x^2 + y^2),
+  native phi = atan2(x, -y), native theta = acos(R) (R in radians); the
+  native-to-celestial rotation with (alpha_p, delta_p) = (CRVAL1, CRVAL2)
+  and phi_p = 180 deg.  Pixels with R > 1 lie outside the projection and
+  have no world coordinate (NaN).
+
+(i, j) are FITS 1-based pixel indices along NAXIS1 / NAXIS2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def wcs_world(wcs: dict, i, j):
+    """World (lon, lat) in degrees for 1-based pixel coordinates (i, j)."""
+    i = np.asarray(i, dtype=np.float64)
+    j = np.asarray(j, dtype=np.float64)
+    x = wcs["cdelt1"] * (i - wcs["crpix1"])
+    y = wcs["cdelt2"] * (j - wcs["crpix2"])
+    proj = wcs["proj"].upper()
+    if proj == "CAR":
+        if wcs.get("crval2", 0.0) != 0.0:
+            raise ValueError("oblique CAR (CRVAL2 != 0) is not supported")
+        lon = np.mod(wcs["crval1"] + x, 360.0)
+        lat = y.copy()
+        bad = np.abs(lat) > 90.0
+        lon = np.where(bad, np.nan, lon)
+        lat = np.where(bad, np.nan, lat)
+        return lon, lat
+    if proj == "SIN":
+        r = np.radians(np.hypot(x, y))
+        phi = np.arctan2(np.radians(x), -np.radians(y))
+        with np.errstate(invalid="ignore"):
+            theta = np.arccos(r)              # NaN outside the disc R > 1
+        ap = np.radians(wcs["crval1"])
+        dp = np.radians(wcs["crval2"])
+        php = np.pi                           # LONPOLE = 180 deg for zenithal
+        dphi = phi - php
+        st, ct = np.sin(theta), np.cos(theta)
+        lat = np.arcsin(np.clip(st * np.sin(dp) + ct * np.cos(dp) * np.cos(dphi), -1.0, 1.0))
+        lon = ap + np.arctan2(-ct * np.sin(dphi), st * np.cos(dp) - ct * np.sin(dp) * np.cos(dphi))
+        lon = np.mod(np.degrees(lon), 360.0)
+        lat = np.degrees(lat)
+        bad = ~np.isfinite(theta)
+        return np.where(bad, np.nan, lon), np.where(bad, np.nan, lat)
+    raise ValueError(f"unsupported projection {proj!r}")
+
+
+def wcs_targets(wcs: dict):
+    """World coordinates of every pixel centre, flattened in FITS order.
+
+    Target t = (j-1) * NAXIS1 + (i-1), i.e. numpy [NAXIS2][NAXIS1] order,
+    which is the layout the paper writes with ``fits.writeto`` (Listing 1).
+    """
+    nx, ny = int(wcs["naxis1"]), int(wcs["naxis2"])
+    jj, ii = np.meshgrid(np.arange(1, ny + 1), np.arange(1, nx + 1), indexing="ij")
+    lon, lat = wcs_world(wcs, ii.ravel(), jj.ravel())
+    return lon, lat
