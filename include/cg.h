@@ -1,0 +1,216 @@
+/*
+ * cg.h - convolution-based gridding on AMD Instinct MI355X (gfx950), C ABI.
+ *
+ * Method: Winkel, Floeer & Lenz (2016), "Cygrid: A fast Cython-powered
+ * convolution-based gridding module for Python", Sect. 2 and 3.
+ *
+ *   S_t[c] = sum_n R_n[c] w(t, n)    Eq. (1)   weighted data sum per channel
+ *   W_t    = sum_n w(t, n)           Eq. (2)   weight map
+ *   R_t[c] = S_t[c] / W_t            Eq. (3)   normalised cube
+ *
+ * for every target t (the pixel centres of a FITS/WCS grid, or a list of
+ * "sight lines"), over the input samples n within the kernel support of t.
+ * Candidate samples are found through a HEALPix RING lookup table (Sect. 2.2,
+ * 3.3); the support test is exact (d <= support, inclusive) and is made in
+ * FP64 on unit vectors, so the result does not depend on the HEALPix
+ * resolution.
+ *
+ * The call sequence mirrors the paper's Python API (Listing 1, Sect. 3.5):
+ *   cg_create_wcs / cg_create_sightlines   (WcsGrid(header) / SlGrid(lon, lat))
+ *   cg_set_kernel                          (set_kernel(type, params, support, hpx_maxres))
+ *   cg_grid                                (grid(lon, lat, signal); accumulates)
+ *   cg_get_datacube / cg_get_weights       (get_datacube(); weight map of Eq. 2)
+ *
+ * Conventions for every entry point:
+ *   - Angles are degrees (Listing 1 passes degrees); longitudes any real
+ *     value (reduced mod 360), latitudes in [-90, 90].
+ *   - "device" pointers are HIP device memory on the handle's device;
+ *     "host" pointers are ordinary host memory.  No pointer is retained
+ *     after the call returns except where stated (sight-line coordinates are
+ *     copied at creation).  Input device buffers must stay valid and
+ *     unmodified until the work queued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is queued on it; calls return without waiting for the
+ *     GPU except where stated.
+ *   - Every call returns a cg_status; nothing throws across the ABI.
+ *     Argument and call-order errors are detected on the host before any
+ *     device work is queued and leave the handle unchanged and usable.
+ *     cg_last_error() returns a thread-local message for the last failure.
+ *   - A handle is used from one host thread at a time and one stream at a
+ *     time; different handles are independent.
+ */
+#ifndef CG_H_
+#define CG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cg_status {
+  CG_OK = 0,
+  CG_E_INVALID = -1,      /* bad argument (null pointer, size, kernel parameter) */
+  CG_E_STATE = -2,        /* call out of order (e.g. grid before set_kernel) */
+  CG_E_OOM = -3,          /* device allocation failed */
+  CG_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  CG_E_DEVICE = -5,       /* a HIP runtime call failed */
+  CG_E_INPUT = -6         /* device-side input error: non-finite or |lat| > 90 */
+} cg_status;
+
+/* element type of the sample data handed to cg_grid */
+typedef enum cg_dtype { CG_F64 = 0, CG_F32 = 1, CG_F16 = 2, CG_BF16 = 3 } cg_dtype;
+
+/* arithmetic of the channel contraction (Eq. 1); distances and the support
+ * test are FP64 and the weight map W is accumulated in FP64 in every mode */
+typedef enum cg_prec {
+  CG_PREC_FP32 = 0,   /* FP32 weights x FP32 data on the vector ALUs, two-level FP64 sums */
+  CG_PREC_BF16 = 1,   /* BF16 weights x BF16 data on the matrix cores (MFMA), FP32 accumulate */
+  CG_PREC_FP16 = 2    /* FP16 weights x FP16 data on the matrix cores (MFMA), FP32 accumulate */
+} cg_prec;
+
+typedef enum cg_kernel_type {
+  CG_GAUSS1D = 0,  /* params = {sigma}: w = exp(-d^2 / (2 sigma^2))            (Listing 1) */
+  CG_GAUSS2D = 1   /* params = {sigma_maj, sigma_min, pa}: elliptical Gaussian in world
+                      coordinates (Sect. 2.1, Fig. 1); pa = position angle of the major
+                      axis, east of north, at the target */
+} cg_kernel_type;
+
+typedef enum cg_proj { CG_PROJ_CAR = 0, CG_PROJ_SIN = 1 } cg_proj;
+
+/* Target grid of a WcsGrid: the subset of a FITS/WCS header that defines the
+ * pixel centres (Listing 1).  CAR requires crval2 == 0 (non-oblique);
+ * SIN uses LONPOLE = 180 deg.  Pixel (i, j) is 1-based along NAXIS1/NAXIS2. */
+typedef struct cg_wcs {
+  int32_t proj;          /* cg_proj */
+  int32_t reserved;      /* must be 0 */
+  int64_t naxis1, naxis2;
+  double crpix1, crpix2; /* reference pixel (1-based) */
+  double crval1, crval2; /* reference world coordinate, degrees */
+  double cdelt1, cdelt2; /* pixel increments, degrees */
+} cg_wcs;
+
+typedef struct cg_gridder cg_gridder;   /* opaque handle */
+
+/* WcsGrid(header) (Sect. 3.5): a gridder whose targets are the pixel
+ * centres of `wcs`, with `nchan` >= 1 channels per target, on the current
+ * HIP device.  The handle owns its accumulators (S: nchan x targets FP32,
+ * W: FP64); they start empty.  Errors: CG_E_INVALID (null pointer, naxis <
+ * 1, nchan < 1, zero cdelt), CG_E_UNSUPPORTED (unknown projection, oblique
+ * CAR), CG_E_OOM, CG_E_DEVICE.  Synchronises the null stream once. */
+cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan);
+
+/* SlGrid(lon, lat) (Sect. 3.5, 5): a gridder whose targets are `ntarget`
+ * arbitrary coordinates ("sight lines").  lon_deg/lat_deg: device FP64
+ * [ntarget], copied into the handle (the caller may free them after the
+ * call returns).  Output order of get_datacube/get_weights is the order
+ * given here.  Targets with non-finite or |lat| > 90 coordinates stay empty
+ * (NaN) and set the sticky input flag.  Synchronises `stream`. */
+cg_status cg_create_sightlines(cg_gridder** out, const double* lon_deg, const double* lat_deg,
+                               int64_t ntarget, int64_t nchan, void* stream);
+
+/* set_kernel(kernel_type, kernel_params, kernel_support, hpx_maxres)
+ * (Listing 1, Sect. 3.5).  params: host double[nparams] (1 for GAUSS1D, 3
+ * for GAUSS2D; sigmas in degrees, 0 < sigma_min <= sigma_maj, pa in
+ * degrees).  support_deg: radius beyond which samples are ignored (0 <
+ * support < 90).  hpx_maxres_deg: resolution of the internal HEALPix grid;
+ * nside = smallest power of two with sqrt(pi/3)/nside <= hpx_maxres (a
+ * speed knob only: the support test is exact), unless cg_set_nside fixed
+ * it.  May be called again; changing the kernel discards nothing already
+ * accumulated.  Errors: CG_E_INVALID. */
+cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params, int32_t nparams,
+                        double support_deg, double hpx_maxres_deg);
+
+/* Fix the internal HEALPix nside (power of two, 1 <= nside <= 8192) instead of
+ * deriving it from hpx_maxres.  Errors: CG_E_INVALID. */
+cg_status cg_set_nside(cg_gridder* g, int64_t nside);
+
+/* Select the contraction arithmetic (cg_prec).  Default CG_PREC_FP32.
+ * Errors: CG_E_INVALID. */
+cg_status cg_set_precision(cg_gridder* g, int32_t prec);
+
+/* grid(lon, lat, signal) (Listing 1; Sect. 2.1 Eq. 1-2): add the
+ * contributions of `nsamples` samples to S and W.  lon_deg, lat_deg: device
+ * FP64 [nsamples].  data: device, `dtype` elements, row n at data + n*ld_data
+ * elements, channel c at column c (one spectrum contiguous); ld_data >=
+ * nchan.  Repeated calls accumulate (chunked input equals one call).
+ * Samples with non-finite or |lat| > 90 coordinates are skipped and set the
+ * sticky input flag reported by cg_sync.  nsamples == 0 is a no-op.
+ * Synchronises `stream` once to size the candidate lists.  Errors:
+ * CG_E_STATE (no kernel set), CG_E_INVALID, CG_E_OOM, CG_E_DEVICE. */
+cg_status cg_grid(cg_gridder* g, const double* lon_deg, const double* lat_deg, const void* data,
+                  int32_t dtype, int64_t nsamples, int64_t ld_data, void* stream);
+
+/* get_datacube() (Listing 1; Eq. 3): out = device FP32 [nchan][naxis2][naxis1]
+ * for a WCS grid (FITS/numpy order) or [nchan][ntarget] for sight lines;
+ * R = S / W where W > 0, NaN elsewhere.  Does not reset the accumulators.
+ * Errors: CG_E_INVALID (null out). */
+cg_status cg_get_datacube(cg_gridder* g, float* out, void* stream);
+
+/* Weight map W of Eq. (2): out = device FP32 [naxis2][naxis1] or [ntarget];
+ * 0 where no sample lies within the support. */
+cg_status cg_get_weights(cg_gridder* g, float* out, void* stream);
+
+/* clear + grid + get_datacube + get_weights in one pass: the accumulators are
+ * left empty and the normalised cube and weight map are written straight to
+ * cube_out / weights_out (layouts as above; weights_out may be NULL).  Same
+ * argument rules and errors as cg_grid. */
+cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* lat_deg,
+                           const void* data, int32_t dtype, int64_t nsamples, int64_t ld_data,
+                           float* cube_out, float* weights_out, void* stream);
+
+/* Reset S and W to empty (Sect. 2.1 step 1). */
+cg_status cg_clear(cg_gridder* g, void* stream);
+
+/* Wait for `stream` and report the sticky device input flag: CG_E_INPUT if
+ * any sample or sight line passed since the last cg_sync had a non-finite
+ * coordinate or |lat| > 90 (the flag is then cleared), CG_E_DEVICE on a HIP
+ * failure, else CG_OK. */
+cg_status cg_sync(cg_gridder* g, void* stream);
+
+/* Neighbour-set statistics for verification: for each target, the number of
+ * samples with d <= support (counts: device int32 [ntarget]) and the sum mod
+ * 2^64 of splitmix64(n) over their input indices n (hashes: device uint64
+ * [ntarget]; may be NULL), found through the same lookup as cg_grid.
+ * Target order as get_weights.  Does not touch the accumulators. */
+cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double* lat_deg,
+                             int64_t nsamples, int32_t* counts, uint64_t* hashes, void* stream);
+
+/* Handle queries (host):  what = 0 ntargets, 1 nchan, 2 nside, 3 ntiles,
+ * 4 candidates in the last grid call, 5 precision, 6 device. */
+cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value);
+
+void cg_destroy(cg_gridder* g);
+const char* cg_last_error(void);
+const char* cg_version(void);
+
+/* ---- host-side helpers (the same code the kernels run; for verification) ----
+ * HEALPix RING functions re-implemented after Gorski et al. 2005 (Sect. 3.2). */
+
+/* RING index of each (lon, lat) in degrees: host arrays [n] -> out[n]. */
+cg_status cg_hpx_ang2pix_ring(int64_t nside, int64_t n, const double* lon_deg, const double* lat_deg,
+                              int64_t* out);
+/* Pixel centres: out_lon/out_lat degrees [n] of RING pixels pix[n]. */
+cg_status cg_hpx_pix2ang_ring(int64_t nside, int64_t n, const int64_t* pix, double* out_lon,
+                              double* out_lat);
+/* Ring of each RING pixel: ring number (1-based) and position in the ring. */
+cg_status cg_hpx_pix2ring(int64_t nside, int64_t n, const int64_t* pix, int64_t* ring, int64_t* j);
+/* Ring table: for ring i (1..4 nside - 1): first index, pixel count, centre z. */
+cg_status cg_hpx_ring_info(int64_t nside, int64_t i, int64_t* start, int64_t* npix, double* z);
+/* Pixel ranges that may hold points within rho_deg of (lon, lat): inclusive
+ * RING ranges written as pairs into ranges[2*k], ranges[2*k+1] (host, at most
+ * max_ranges pairs); *nranges receives the count.  CG_E_INVALID if
+ * max_ranges is too small. */
+cg_status cg_hpx_cap_ranges(int64_t nside, double lon_deg, double lat_deg, double rho_deg,
+                            int64_t* ranges, int64_t max_ranges, int64_t* nranges);
+/* WCS pixel centres (host): world coordinates of 1-based pixels (i, j);
+ * NaN where the pixel has none. */
+cg_status cg_wcs_pix2world(const cg_wcs* wcs, int64_t n, const double* i, const double* j,
+                           double* lon_deg, double* lat_deg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CG_H_ */

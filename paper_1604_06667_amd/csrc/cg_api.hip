@@ -1,0 +1,682 @@
+// C ABI of libcg: handles, argument checks, workspace and launch sequence.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/cg.h"
+#include "cg_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+cg_status fail(cg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+cg_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(CG_E_OOM, "%s: out of device memory", what);
+  return fail(CG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define CG_HIP(call, what)                          \
+  do {                                              \
+    hipError_t e_ = (call);                         \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (b.bytes >= bytes) return hipSuccess;
+  b.release();
+  // grow geometrically so that slowly growing inputs do not reallocate every call
+  const size_t want = bytes + bytes / 8;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return e;
+  }
+  b.bytes = want;
+  return hipSuccess;
+}
+
+constexpr double kDeg = cg::hpx::kPi / 180.0;
+constexpr double kLog2e = 1.44269504088896340736;
+
+int bits_for(uint64_t v) {
+  int b = 0;
+  while (b < 32 && (1ull << b) <= v) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct cg_gridder {
+  int device = 0;
+  int kind = 0;  // 0 WCS grid, 1 sight lines
+  cg::WcsDev wcs{};
+  int64_t ntarget = 0, nchan = 0;
+  int64_t tile_w = 8, tile_h = 8, ntx = 0, nty = 0, ntiles = 0, nslots = 0;
+  DevBuf txyz, tll, slot_target, target_slot, caps;
+  bool kernel_set = false;
+  cg::KernelParams kp{};
+  double support_rad = 0.0;
+  int64_t nside = 0;
+  bool nside_fixed = false;
+  int prec = CG_PREC_FP32;
+  bool span_valid = false;
+  DevBuf ring_first, span_bound, range_off;
+  int64_t total_ranges = 0;
+  DevBuf S, W;
+  bool fresh = true;
+  DevBuf flag;
+  DevBuf keys, vals, keys2, vals2, hist, ring_off, sx, sdata, ranges, nranges, ncand, cand_off,
+      cand;
+  const uint32_t* sorted_keys = nullptr;
+  const uint32_t* sorted_vals = nullptr;
+  int64_t last_n = 0;
+  int64_t last_ncand = 0;
+  uint64_t* h_word = nullptr;  // pinned host word
+};
+
+namespace {
+
+cg_status set_dev(const cg_gridder* g) {
+  CG_HIP(hipSetDevice(g->device), "hipSetDevice");
+  return CG_OK;
+}
+
+cg_status alloc_targets(cg_gridder* g) {
+  CG_HIP(ensure(g->txyz, sizeof(double) * 3 * g->nslots), "alloc targets");
+  CG_HIP(ensure(g->tll, sizeof(double) * 2 * g->nslots), "alloc targets");
+  CG_HIP(ensure(g->slot_target, sizeof(int32_t) * g->nslots), "alloc targets");
+  CG_HIP(ensure(g->target_slot, sizeof(int32_t) * (g->ntarget > 0 ? g->ntarget : 1)),
+         "alloc targets");
+  CG_HIP(ensure(g->caps, sizeof(double) * 4 * (g->ntiles > 0 ? g->ntiles : 1)), "alloc caps");
+  CG_HIP(ensure(g->W, sizeof(double) * g->nslots), "alloc weights");
+  CG_HIP(ensure(g->flag, sizeof(int)), "alloc flag");
+  CG_HIP(hipMemset(g->flag.p, 0, sizeof(int)), "clear flag");
+  CG_HIP(hipHostMalloc((void**)&g->h_word, sizeof(uint64_t) * 2, hipHostMallocDefault),
+         "pinned word");
+  return CG_OK;
+}
+
+// Ring spans and range-slot offsets of the tiles: depend on targets, support
+// and nside only, so they are computed once per set_kernel.
+cg_status ensure_span(cg_gridder* g, hipStream_t st) {
+  if (g->span_valid) return CG_OK;
+  const int64_t nt = g->ntiles;
+  CG_HIP(ensure(g->ring_first, sizeof(int32_t) * (nt > 0 ? nt : 1)), "alloc span");
+  CG_HIP(ensure(g->span_bound, sizeof(uint64_t) * (nt > 0 ? nt : 1)), "alloc span");
+  CG_HIP(ensure(g->range_off, sizeof(uint64_t) * (nt + 1)), "alloc span");
+  const double rho_extra = g->support_rad + 1e-9;
+  CG_HIP(cg::launch_tile_span(g->caps.as<double>(), nt, g->nside, rho_extra,
+                              g->ring_first.as<int32_t>(), g->span_bound.as<uint64_t>(), st),
+         "tile span");
+  CG_HIP(cg::scan_u64(g->span_bound.as<uint64_t>(), g->range_off.as<uint64_t>(), nt, st),
+         "scan span");
+  CG_HIP(hipMemcpyAsync(g->h_word, g->range_off.as<uint64_t>() + nt, sizeof(uint64_t),
+                        hipMemcpyDeviceToHost, st),
+         "read span");
+  CG_HIP(hipStreamSynchronize(st), "sync span");
+  g->total_ranges = (int64_t)g->h_word[0];
+  CG_HIP(ensure(g->ranges, sizeof(uint32_t) * 2 * (g->total_ranges > 0 ? g->total_ranges : 1)),
+         "alloc ranges");
+  CG_HIP(ensure(g->nranges, sizeof(uint32_t) * (nt > 0 ? nt : 1)), "alloc ranges");
+  CG_HIP(ensure(g->ncand, sizeof(uint64_t) * (nt > 0 ? nt : 1)), "alloc ranges");
+  CG_HIP(ensure(g->cand_off, sizeof(uint64_t) * (nt + 1)), "alloc ranges");
+  g->span_valid = true;
+  return CG_OK;
+}
+
+bool small_c(const cg_gridder* g) { return g->nchan <= cg::kSmallC && g->prec == CG_PREC_FP32; }
+
+// HEALPix index, sort, ring offsets, permute and candidate lists for n samples.
+cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_t n,
+                     const void* data, int32_t dtype, int64_t ld, bool with_data, hipStream_t st) {
+  cg_status s = ensure_span(g, st);
+  if (s != CG_OK) return s;
+  const int64_t nside = g->nside;
+  CG_HIP(ensure(g->keys, sizeof(uint32_t) * n), "alloc keys");
+  CG_HIP(ensure(g->vals, sizeof(uint32_t) * n), "alloc keys");
+  CG_HIP(ensure(g->keys2, sizeof(uint32_t) * n), "alloc keys");
+  CG_HIP(ensure(g->vals2, sizeof(uint32_t) * n), "alloc keys");
+  CG_HIP(ensure(g->hist, sizeof(uint32_t) * cg::radix_hist_elems(n)), "alloc hist");
+  CG_HIP(ensure(g->ring_off, sizeof(uint32_t) * (4 * nside + 1)), "alloc ring offsets");
+  CG_HIP(ensure(g->sx, sizeof(double) * 3 * n), "alloc sorted vectors");
+  if (with_data) CG_HIP(ensure(g->sdata, sizeof(float) * n * g->nchan), "alloc sorted data");
+  CG_HIP(cg::launch_prep(lon, lat, n, nside, g->keys.as<uint32_t>(), g->vals.as<uint32_t>(),
+                         g->flag.as<int>(), st),
+         "prep");
+  bool in_tmp = false;
+  const int bits = bits_for((uint64_t)cg::hpx::npix(nside));
+  CG_HIP(cg::radix_sort(g->keys.as<uint32_t>(), g->vals.as<uint32_t>(), g->keys2.as<uint32_t>(),
+                        g->vals2.as<uint32_t>(), g->hist.as<uint32_t>(), n, bits, &in_tmp, st),
+         "radix sort");
+  g->sorted_keys = in_tmp ? g->keys2.as<uint32_t>() : g->keys.as<uint32_t>();
+  g->sorted_vals = in_tmp ? g->vals2.as<uint32_t>() : g->vals.as<uint32_t>();
+  uint32_t* roff = g->ring_off.as<uint32_t>();
+  CG_HIP(cg::launch_ring_offsets(g->sorted_keys, n, nside, roff, st), "ring offsets");
+  CG_HIP(cg::launch_permute(g->sorted_vals, roff + 4 * nside, n, lon, lat, data, dtype, ld,
+                            g->nchan, with_data, n, g->sx.as<double>(), g->sdata.as<float>(), st),
+         "permute");
+  CG_HIP(cg::launch_tile_ranges(g->caps.as<double>(), g->ntiles, nside, g->support_rad + 1e-9,
+                                g->ring_first.as<int32_t>(), g->range_off.as<uint64_t>(),
+                                g->sorted_keys, roff, g->ranges.as<uint32_t>(),
+                                g->nranges.as<uint32_t>(), g->ncand.as<uint64_t>(), st),
+         "tile ranges");
+  CG_HIP(cg::scan_u64(g->ncand.as<uint64_t>(), g->cand_off.as<uint64_t>(), g->ntiles, st),
+         "scan candidates");
+  CG_HIP(hipMemcpyAsync(g->h_word, g->cand_off.as<uint64_t>() + g->ntiles, sizeof(uint64_t),
+                        hipMemcpyDeviceToHost, st),
+         "read candidates");
+  CG_HIP(hipStreamSynchronize(st), "sync candidates");
+  const int64_t total = (int64_t)g->h_word[0];
+  g->last_ncand = total;
+  g->last_n = n;
+  CG_HIP(ensure(g->cand, sizeof(uint32_t) * (total > 0 ? total : 1)), "alloc candidates");
+  CG_HIP(cg::launch_expand(g->range_off.as<uint64_t>(), g->ranges.as<uint32_t>(),
+                           g->nranges.as<uint32_t>(), g->cand_off.as<uint64_t>(), g->ntiles,
+                           g->cand.as<uint32_t>(), st),
+         "expand");
+  return CG_OK;
+}
+
+cg::TileView tile_view(const cg_gridder* g) {
+  cg::TileView tv;
+  tv.txyz = g->txyz.as<double>();
+  tv.tll = g->tll.as<double>();
+  tv.cand_off = g->cand_off.as<uint64_t>();
+  tv.cand = g->cand.as<uint32_t>();
+  tv.sx = g->sx.as<double>();
+  tv.nslots = g->nslots;
+  tv.nsorted = g->last_n;
+  return tv;
+}
+
+cg_status check_grid_args(const cg_gridder* g, const double* lon, const double* lat,
+                          const void* data, int32_t dtype, int64_t n, int64_t ld) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (!g->kernel_set) return fail(CG_E_STATE, "set_kernel must be called before grid");
+  if (n < 0) return fail(CG_E_INVALID, "nsamples < 0");
+  if (n > 0xFFFFFFFFll - 1) return fail(CG_E_UNSUPPORTED, "nsamples >= 2^32 (split into chunks)");
+  if (n == 0) return CG_OK;
+  if (!lon || !lat || !data) return fail(CG_E_INVALID, "null coordinate or data pointer");
+  if (dtype < CG_F64 || dtype > CG_BF16) return fail(CG_E_INVALID, "unknown dtype %d", dtype);
+  if (ld < g->nchan) return fail(CG_E_INVALID, "ld_data (%lld) < nchan (%lld)", (long long)ld,
+                                 (long long)g->nchan);
+  return CG_OK;
+}
+
+cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
+                   const cg::OutView& ov, hipStream_t st) {
+  const cg::TileView tv = tile_view(g);
+  if (g->prec == CG_PREC_FP32) {
+    CG_HIP(cg::launch_gather_fp32(tv, g->kp, g->ntiles, g->sorted_vals, data, dtype, ld,
+                                  g->sdata.as<float>(), g->nchan, ov, st),
+           "gather");
+  } else {
+    CG_HIP(cg::launch_gather_mfma(tv, g->kp, g->ntiles, g->sorted_vals, data, dtype, ld, g->nchan,
+                                  g->prec, ov, st),
+           "gather (mfma)");
+  }
+  return CG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cg_last_error(void) { return g_err.c_str(); }
+const char* cg_version(void) { return "cg 0.1 (gfx950)"; }
+
+cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan) {
+  if (!out || !wcs) return fail(CG_E_INVALID, "null pointer");
+  *out = nullptr;
+  if (wcs->proj != CG_PROJ_CAR && wcs->proj != CG_PROJ_SIN)
+    return fail(CG_E_UNSUPPORTED, "unknown projection %d", wcs->proj);
+  if (wcs->reserved != 0) return fail(CG_E_INVALID, "reserved field must be 0");
+  if (wcs->naxis1 < 1 || wcs->naxis2 < 1) return fail(CG_E_INVALID, "naxis must be >= 1");
+  if (nchan < 1 || nchan > 65535) return fail(CG_E_INVALID, "nchan must be in [1, 65535]");
+  if (!(wcs->cdelt1 != 0.0 && wcs->cdelt2 != 0.0 && isfinite(wcs->cdelt1) &&
+        isfinite(wcs->cdelt2) && isfinite(wcs->crpix1) && isfinite(wcs->crpix2) &&
+        isfinite(wcs->crval1) && isfinite(wcs->crval2)))
+    return fail(CG_E_INVALID, "WCS keywords must be finite with non-zero CDELT");
+  if (wcs->proj == CG_PROJ_CAR && wcs->crval2 != 0.0)
+    return fail(CG_E_UNSUPPORTED, "oblique CAR (CRVAL2 != 0) is not supported");
+  if (fabs(wcs->crval2) > 90.0) return fail(CG_E_INVALID, "|CRVAL2| > 90");
+  const int64_t nt = wcs->naxis1 * wcs->naxis2;
+  if (nt >= (1ll << 31) - 64) return fail(CG_E_UNSUPPORTED, "grid too large");
+  cg_gridder* g = new cg_gridder();
+  (void)hipGetDevice(&g->device);
+  g->kind = 0;
+  g->wcs.proj = wcs->proj;
+  g->wcs.naxis1 = wcs->naxis1;
+  g->wcs.naxis2 = wcs->naxis2;
+  g->wcs.crpix1 = wcs->crpix1;
+  g->wcs.crpix2 = wcs->crpix2;
+  g->wcs.crval1 = wcs->crval1;
+  g->wcs.crval2 = wcs->crval2;
+  g->wcs.cdelt1 = wcs->cdelt1;
+  g->wcs.cdelt2 = wcs->cdelt2;
+  g->ntarget = nt;
+  g->nchan = nchan;
+  g->ntx = (wcs->naxis1 + g->tile_w - 1) / g->tile_w;
+  g->nty = (wcs->naxis2 + g->tile_h - 1) / g->tile_h;
+  g->ntiles = g->ntx * g->nty;
+  g->nslots = g->ntiles * cg::kTile;
+  cg_status s = alloc_targets(g);
+  if (s == CG_OK) {
+    hipError_t e = cg::launch_wcs_targets(g->wcs, g->tile_w, g->tile_h, g->ntx, g->nslots,
+                                          g->txyz.as<double>(), g->tll.as<double>(),
+                                          g->slot_target.as<int32_t>(),
+                                          g->target_slot.as<int32_t>(), nullptr);
+    if (e == hipSuccess)
+      e = cg::launch_tile_caps(g->txyz.as<double>(), g->nslots, g->ntiles, g->caps.as<double>(),
+                               nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) s = hip_fail(e, "target setup");
+  }
+  if (s != CG_OK) {
+    cg_destroy(g);
+    return s;
+  }
+  *out = g;
+  return CG_OK;
+}
+
+cg_status cg_create_sightlines(cg_gridder** out, const double* lon_deg, const double* lat_deg,
+                               int64_t ntarget, int64_t nchan, void* stream) {
+  if (!out) return fail(CG_E_INVALID, "null pointer");
+  *out = nullptr;
+  if (ntarget < 1) return fail(CG_E_INVALID, "ntarget must be >= 1");
+  if (!lon_deg || !lat_deg) return fail(CG_E_INVALID, "null coordinate pointer");
+  if (nchan < 1 || nchan > 65535) return fail(CG_E_INVALID, "nchan must be in [1, 65535]");
+  if (ntarget >= (1ll << 31) - 64) return fail(CG_E_UNSUPPORTED, "too many targets");
+  hipStream_t st = (hipStream_t)stream;
+  cg_gridder* g = new cg_gridder();
+  (void)hipGetDevice(&g->device);
+  g->kind = 1;
+  g->ntarget = ntarget;
+  g->nchan = nchan;
+  g->ntiles = (ntarget + cg::kTile - 1) / cg::kTile;
+  g->nslots = g->ntiles * cg::kTile;
+  cg_status s = alloc_targets(g);
+  DevBuf k1, v1, k2, v2, h;
+  if (s == CG_OK) {
+    hipError_t e = ensure(k1, 4 * ntarget);
+    if (e == hipSuccess) e = ensure(v1, 4 * ntarget);
+    if (e == hipSuccess) e = ensure(k2, 4 * ntarget);
+    if (e == hipSuccess) e = ensure(v2, 4 * ntarget);
+    if (e == hipSuccess) e = ensure(h, 4 * cg::radix_hist_elems(ntarget));
+    if (e == hipSuccess)
+      e = cg::launch_sl_keys(lon_deg, lat_deg, ntarget, k1.as<uint32_t>(), v1.as<uint32_t>(),
+                             g->flag.as<int>(), st);
+    bool in_tmp = false;
+    if (e == hipSuccess)
+      e = cg::radix_sort(k1.as<uint32_t>(), v1.as<uint32_t>(), k2.as<uint32_t>(),
+                         v2.as<uint32_t>(), h.as<uint32_t>(), ntarget,
+                         bits_for((uint64_t)cg::hpx::npix(8192)), &in_tmp, st);
+    if (e == hipSuccess)
+      e = cg::launch_sl_targets(lon_deg, lat_deg, in_tmp ? v2.as<uint32_t>() : v1.as<uint32_t>(),
+                                ntarget, g->nslots, g->txyz.as<double>(), g->tll.as<double>(),
+                                g->slot_target.as<int32_t>(), g->target_slot.as<int32_t>(), st);
+    if (e == hipSuccess)
+      e = cg::launch_tile_caps(g->txyz.as<double>(), g->nslots, g->ntiles, g->caps.as<double>(),
+                               st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = hip_fail(e, "sight-line setup");
+  }
+  k1.release(); v1.release(); k2.release(); v2.release(); h.release();
+  if (s != CG_OK) {
+    cg_destroy(g);
+    return s;
+  }
+  *out = g;
+  return CG_OK;
+}
+
+cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params, int32_t nparams,
+                        double support_deg, double hpx_maxres_deg) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (!params) return fail(CG_E_INVALID, "null params");
+  cg::KernelParams kp{};
+  if (kernel_type == CG_GAUSS1D) {
+    if (nparams != 1) return fail(CG_E_INVALID, "gauss1d takes 1 parameter (sigma)");
+    const double s = params[0] * kDeg;
+    if (!(s > 0.0) || !isfinite(s)) return fail(CG_E_INVALID, "sigma must be > 0");
+    kp.type = 0;
+    kp.k1 = kLog2e / (2.0 * s * s);
+  } else if (kernel_type == CG_GAUSS2D) {
+    if (nparams != 3) return fail(CG_E_INVALID, "gauss2d takes 3 parameters (sigma_maj, sigma_min, pa)");
+    const double a = params[0] * kDeg, b = params[1] * kDeg, pa = params[2] * kDeg;
+    if (!(a > 0.0 && b > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(pa))
+      return fail(CG_E_INVALID, "sigmas must be > 0 and pa finite");
+    if (b > a) return fail(CG_E_INVALID, "sigma_min must not exceed sigma_maj");
+    kp.type = 1;
+    kp.kmaj = kLog2e / (2.0 * a * a);
+    kp.kmin = kLog2e / (2.0 * b * b);
+    kp.cospa = cos(pa);
+    kp.sinpa = sin(pa);
+  } else {
+    return fail(CG_E_INVALID, "unknown kernel type %d", kernel_type);
+  }
+  if (!(support_deg > 0.0 && support_deg < 90.0))
+    return fail(CG_E_INVALID, "support must be in (0, 90) degrees");
+  const double rs = support_deg * kDeg;
+  const double c = 2.0 * sin(0.5 * rs);
+  kp.cs2 = c * c;
+  int64_t nside = g->nside;
+  if (!g->nside_fixed) {
+    if (!(hpx_maxres_deg > 0.0) || !isfinite(hpx_maxres_deg))
+      return fail(CG_E_INVALID, "hpx_maxres must be > 0 (or fix nside with cg_set_nside)");
+    const double res = hpx_maxres_deg * kDeg;
+    nside = 1;
+    while (nside < 8192 && sqrt(cg::hpx::kPi / 3.0) / (double)nside > res) nside *= 2;
+  }
+  g->kp = kp;
+  g->support_rad = rs;
+  g->nside = nside;
+  g->kernel_set = true;
+  g->span_valid = false;
+  return CG_OK;
+}
+
+cg_status cg_set_nside(cg_gridder* g, int64_t nside) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (nside < 1 || nside > 8192 || (nside & (nside - 1)) != 0)
+    return fail(CG_E_INVALID, "nside must be a power of two in [1, 8192]");
+  g->nside = nside;
+  g->nside_fixed = true;
+  g->span_valid = false;
+  return CG_OK;
+}
+
+cg_status cg_set_precision(cg_gridder* g, int32_t prec) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (prec < CG_PREC_FP32 || prec > CG_PREC_FP16) return fail(CG_E_INVALID, "unknown precision %d", prec);
+  if (prec != CG_PREC_FP32 && !cg::mfma_available())
+    return fail(CG_E_UNSUPPORTED, "matrix-core contraction not built");
+  g->prec = prec;
+  return CG_OK;
+}
+
+cg_status cg_grid(cg_gridder* g, const double* lon_deg, const double* lat_deg, const void* data,
+                  int32_t dtype, int64_t nsamples, int64_t ld_data, void* stream) {
+  cg_status s = check_grid_args(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data);
+  if (s != CG_OK || nsamples == 0) return s;
+  if ((s = set_dev(g)) != CG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  CG_HIP(ensure(g->S, sizeof(float) * g->nchan * g->nslots), "alloc accumulators");
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g), st);
+  if (s != CG_OK) return s;
+  cg::OutView ov{};
+  ov.S = g->S.as<float>();
+  ov.W = g->W.as<double>();
+  ov.slot_target = g->slot_target.as<int32_t>();
+  ov.ntarget = g->ntarget;
+  ov.mode = g->fresh ? cg::ACC_OVERWRITE : cg::ACC_ADD;
+  s = contract(g, data, dtype, ld_data, ov, st);
+  if (s == CG_OK) g->fresh = false;
+  return s;
+}
+
+cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* lat_deg,
+                           const void* data, int32_t dtype, int64_t nsamples, int64_t ld_data,
+                           float* cube_out, float* weights_out, void* stream) {
+  cg_status s = check_grid_args(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data);
+  if (s != CG_OK) return s;
+  if (!cube_out) return fail(CG_E_INVALID, "null cube_out");
+  if ((s = set_dev(g)) != CG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  g->fresh = true;
+  if (nsamples == 0) {
+    CG_HIP(cg::launch_fill(cube_out, g->nchan * g->ntarget, __builtin_nanf(""), st), "fill");
+    if (weights_out) CG_HIP(cg::launch_fill(weights_out, g->ntarget, 0.0f, st), "fill");
+    return CG_OK;
+  }
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g), st);
+  if (s != CG_OK) return s;
+  cg::OutView ov{};
+  ov.cube = cube_out;
+  ov.wout = weights_out;
+  ov.slot_target = g->slot_target.as<int32_t>();
+  ov.ntarget = g->ntarget;
+  ov.mode = cg::ACC_FINAL;
+  return contract(g, data, dtype, ld_data, ov, st);
+}
+
+cg_status cg_get_datacube(cg_gridder* g, float* out, void* stream) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (!out) return fail(CG_E_INVALID, "null output");
+  cg_status s = set_dev(g);
+  if (s != CG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (g->fresh) {
+    CG_HIP(cg::launch_fill(out, g->nchan * g->ntarget, __builtin_nanf(""), st), "fill");
+    return CG_OK;
+  }
+  CG_HIP(cg::launch_normalize(g->S.as<float>(), g->W.as<double>(), g->target_slot.as<int32_t>(),
+                              g->nslots, g->nchan, g->ntarget, out, nullptr, st),
+         "normalize");
+  return CG_OK;
+}
+
+cg_status cg_get_weights(cg_gridder* g, float* out, void* stream) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (!out) return fail(CG_E_INVALID, "null output");
+  cg_status s = set_dev(g);
+  if (s != CG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (g->fresh) {
+    CG_HIP(cg::launch_fill(out, g->ntarget, 0.0f, st), "fill");
+    return CG_OK;
+  }
+  CG_HIP(cg::launch_normalize(nullptr, g->W.as<double>(), g->target_slot.as<int32_t>(), g->nslots,
+                              g->nchan, g->ntarget, nullptr, out, st),
+         "weights");
+  return CG_OK;
+}
+
+cg_status cg_clear(cg_gridder* g, void* stream) {
+  (void)stream;
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  g->fresh = true;
+  return CG_OK;
+}
+
+cg_status cg_sync(cg_gridder* g, void* stream) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  cg_status s = set_dev(g);
+  if (s != CG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  CG_HIP(hipStreamSynchronize(st), "sync");
+  int f = 0;
+  CG_HIP(hipMemcpy(&f, g->flag.p, sizeof(int), hipMemcpyDeviceToHost), "read flag");
+  if (f) {
+    CG_HIP(hipMemset(g->flag.p, 0, sizeof(int)), "clear flag");
+    return fail(CG_E_INPUT, "input contained non-finite coordinates or |lat| > 90 (skipped)");
+  }
+  return CG_OK;
+}
+
+cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double* lat_deg,
+                             int64_t nsamples, int32_t* counts, uint64_t* hashes, void* stream) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (!g->kernel_set) return fail(CG_E_STATE, "set_kernel must be called first");
+  if (!counts) return fail(CG_E_INVALID, "null counts");
+  if (nsamples < 0 || nsamples > 0xFFFFFFFFll - 1) return fail(CG_E_INVALID, "bad nsamples");
+  cg_status s = set_dev(g);
+  if (s != CG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (nsamples == 0) {
+    CG_HIP(cg::launch_fill(reinterpret_cast<float*>(counts), g->ntarget, 0.0f, st), "clear counts");
+    if (hashes)
+      CG_HIP(cg::launch_fill(reinterpret_cast<float*>(hashes), 2 * g->ntarget, 0.0f, st),
+             "clear hashes");
+    return CG_OK;
+  }
+  if (!lon_deg || !lat_deg) return fail(CG_E_INVALID, "null coordinate pointer");
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, nullptr, CG_F32, g->nchan, false, st);
+  if (s != CG_OK) return s;
+  CG_HIP(cg::launch_stats(tile_view(g), g->kp, g->ntiles, g->sorted_vals,
+                          g->slot_target.as<int32_t>(), counts, hashes, st),
+         "stats");
+  return CG_OK;
+}
+
+cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value) {
+  if (!g || !value) return fail(CG_E_INVALID, "null pointer");
+  switch (what) {
+    case 0: *value = g->ntarget; break;
+    case 1: *value = g->nchan; break;
+    case 2: *value = g->nside; break;
+    case 3: *value = g->ntiles; break;
+    case 4: *value = g->last_ncand; break;
+    case 5: *value = g->prec; break;
+    case 6: *value = g->device; break;
+    default: return fail(CG_E_INVALID, "unknown query %d", what);
+  }
+  return CG_OK;
+}
+
+void cg_destroy(cg_gridder* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  DevBuf* bufs[] = {&g->txyz, &g->tll, &g->slot_target, &g->target_slot, &g->caps,
+                    &g->ring_first, &g->span_bound, &g->range_off, &g->S, &g->W, &g->flag,
+                    &g->keys, &g->vals, &g->keys2, &g->vals2, &g->hist, &g->ring_off, &g->sx,
+                    &g->sdata, &g->ranges, &g->nranges, &g->ncand, &g->cand_off, &g->cand};
+  for (DevBuf* b : bufs) b->release();
+  if (g->h_word) (void)hipHostFree(g->h_word);
+  delete g;
+}
+
+// ------------------------------------------------------------ host helpers
+
+cg_status cg_hpx_ang2pix_ring(int64_t nside, int64_t n, const double* lon_deg,
+                              const double* lat_deg, int64_t* out) {
+  if (nside < 1 || nside > 8192 || n < 0 || (n > 0 && (!lon_deg || !lat_deg || !out)))
+    return fail(CG_E_INVALID, "bad arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    double am = fmod(lon_deg[i], 360.0);
+    if (am < 0.0) am += 360.0;
+    const double d = lat_deg[i] * kDeg;
+    out[i] = cg::hpx::ang2pix_ring(nside, sin(d), cos(d), am * kDeg);
+  }
+  return CG_OK;
+}
+
+cg_status cg_hpx_pix2ang_ring(int64_t nside, int64_t n, const int64_t* pix, double* out_lon,
+                              double* out_lat) {
+  if (nside < 1 || nside > 8192 || n < 0 || (n > 0 && (!pix || !out_lon || !out_lat)))
+    return fail(CG_E_INVALID, "bad arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    if (pix[i] < 0 || pix[i] >= cg::hpx::npix(nside)) return fail(CG_E_INVALID, "pixel out of range");
+    double z, phi;
+    cg::hpx::pix2ang_ring(nside, pix[i], &z, &phi);
+    out_lon[i] = phi / kDeg;
+    out_lat[i] = asin(z) / kDeg;
+  }
+  return CG_OK;
+}
+
+cg_status cg_hpx_pix2ring(int64_t nside, int64_t n, const int64_t* pix, int64_t* ring,
+                          int64_t* j) {
+  if (nside < 1 || nside > 8192 || n < 0 || (n > 0 && (!pix || !ring || !j)))
+    return fail(CG_E_INVALID, "bad arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    if (pix[i] < 0 || pix[i] >= cg::hpx::npix(nside)) return fail(CG_E_INVALID, "pixel out of range");
+    cg::hpx::pix2ring(nside, pix[i], &ring[i], &j[i]);
+  }
+  return CG_OK;
+}
+
+cg_status cg_hpx_ring_info(int64_t nside, int64_t i, int64_t* start, int64_t* npix, double* z) {
+  if (nside < 1 || nside > 8192 || i < 1 || i > 4 * nside - 1 || !start || !npix || !z)
+    return fail(CG_E_INVALID, "bad arguments");
+  *start = cg::hpx::ring_start(nside, i);
+  *npix = cg::hpx::ring_npix(nside, i);
+  *z = cg::hpx::ring_z(nside, i);
+  return CG_OK;
+}
+
+cg_status cg_hpx_cap_ranges(int64_t nside, double lon_deg, double lat_deg, double rho_deg,
+                            int64_t* ranges, int64_t max_ranges, int64_t* nranges) {
+  if (nside < 1 || nside > 8192 || !ranges || !nranges || !(rho_deg >= 0.0))
+    return fail(CG_E_INVALID, "bad arguments");
+  const double d = lat_deg * kDeg;
+  double am = fmod(lon_deg, 360.0);
+  if (am < 0.0) am += 360.0;
+  const double cz = sin(d), cs = cos(d), cphi = am * kDeg, rho = rho_deg * kDeg;
+  int64_t f, l;
+  cg::hpx::cap_ring_span(nside, cz, cs, rho, &f, &l);
+  int64_t k = 0;
+  for (int64_t i = f; i <= l; ++i) {
+    int64_t lo[2], hi[2];
+    const int nr = cg::hpx::ring_cap_ranges(nside, i, cz, cs, cphi, rho, lo, hi);
+    for (int q = 0; q < nr; ++q) {
+      if (k >= max_ranges) return fail(CG_E_INVALID, "max_ranges too small");
+      ranges[2 * k] = lo[q];
+      ranges[2 * k + 1] = hi[q];
+      ++k;
+    }
+  }
+  *nranges = k;
+  return CG_OK;
+}
+
+cg_status cg_wcs_pix2world(const cg_wcs* wcs, int64_t n, const double* i, const double* j,
+                           double* lon_deg, double* lat_deg) {
+  if (!wcs || n < 0 || (n > 0 && (!i || !j || !lon_deg || !lat_deg)))
+    return fail(CG_E_INVALID, "bad arguments");
+  if (wcs->proj != CG_PROJ_CAR && wcs->proj != CG_PROJ_SIN)
+    return fail(CG_E_UNSUPPORTED, "unknown projection");
+  if (wcs->proj == CG_PROJ_CAR && wcs->crval2 != 0.0)
+    return fail(CG_E_UNSUPPORTED, "oblique CAR (CRVAL2 != 0) is not supported");
+  cg::WcsDev w;
+  w.proj = wcs->proj;
+  w.naxis1 = wcs->naxis1;
+  w.naxis2 = wcs->naxis2;
+  w.crpix1 = wcs->crpix1;
+  w.crpix2 = wcs->crpix2;
+  w.crval1 = wcs->crval1;
+  w.crval2 = wcs->crval2;
+  w.cdelt1 = wcs->cdelt1;
+  w.cdelt2 = wcs->cdelt2;
+  for (int64_t k = 0; k < n; ++k) {
+    double lo, la;
+    if (cg::wcs_pix2world(w, i[k], j[k], &lo, &la)) {
+      lon_deg[k] = lo;
+      lat_deg[k] = la;
+    } else {
+      lon_deg[k] = lat_deg[k] = __builtin_nan("");
+    }
+  }
+  return CG_OK;
+}
+
+}  // extern "C"

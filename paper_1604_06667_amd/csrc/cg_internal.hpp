@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP translation units of libcg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "healpix.hpp"
+#include "wcs.hpp"
+
+namespace cg {
+
+constexpr int kTile = 64;              // targets per tile (one wavefront of target slots)
+constexpr int kSmallC = 16;            // up to this many channels the FP32 path stages sorted rows
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;         // keys per thread per radix block
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+// Kernel constants derived on the host by set_kernel.
+struct KernelParams {
+  int type;          // 0 gauss1d, 1 gauss2d
+  double cs2;        // squared chord of the support radius: d <= r_s  <=>  c^2 <= cs2
+  double k1;         // gauss1d: log2(e) / (2 sigma^2)   (exponent in base 2, per rad^2)
+  double kmaj, kmin; // gauss2d: log2(e) / (2 sigma_maj^2), log2(e) / (2 sigma_min^2)
+  double cospa, sinpa;
+};
+
+// Device-side description of one tile's candidate list and target slots.
+struct TileView {
+  const double* txyz;          // [3][nslots] target unit vectors (NaN: no target)
+  const double* tll;           // [2][nslots] target lon, lat in radians (gauss2d axes)
+  const uint64_t* cand_off;    // [ntiles + 1] candidate offsets
+  const uint32_t* cand;        // sorted-sample positions
+  const double* sx;            // [3][nvalid] sorted sample unit vectors
+  int64_t nslots;
+  int64_t nsorted;
+};
+
+// ---------------------------------------------------------------- device math
+
+// (2 asin(c/2))^2 from the squared chord c^2: the true angular distance
+// squared.  Series c^2 (1 + c^2/12 + c^4/90 + c^6/560) for short chords.
+__device__ __forceinline__ double chord2_to_d2(double c2) {
+  if (c2 > 2.5e-3) {
+    const double d = 2.0 * asin(0.5 * sqrt(c2));
+    return d * d;
+  }
+  return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0))));
+}
+
+// 2^(-x) for x >= 0 given in FP64, evaluated as 2^-frac (FP32) * 2^-int so
+// that rounding x to FP32 does not cost accuracy at large x.
+__device__ __forceinline__ float exp2_neg(double x) {
+  const double xi = floor(x);
+  const float f = (float)(x - xi);
+  const int e = (int)xi;
+  if (e > 126) return 0.0f;
+  return ldexpf(exp2f(-f), -e);
+}
+
+// Kernel weight for a pair with chord vector (dx, dy, dz) = p_n - p_t and
+// c2 = |p_n - p_t|^2 <= cs2.  Elliptical: the bearing of the great circle
+// from the target towards the sample is the direction of the chord's
+// projection on the tangent plane at the target; with a, b the unit
+// vectors of the major and minor axis there, u = d.a, v = d.b and
+// cos^2(beta - pa) = u^2 / (u^2 + v^2).
+__device__ __forceinline__ float pair_weight(const KernelParams& kp, double c2, double dx, double dy,
+                                             double dz, double ax, double ay, double az, double bx,
+                                             double by, double bz) {
+  const double d2 = chord2_to_d2(c2);
+  if (kp.type == 0) return exp2_neg(d2 * kp.k1);
+  const double u = dx * ax + dy * ay + dz * az;
+  const double v = dx * bx + dy * by + dz * bz;
+  const double uv = u * u + v * v;
+  if (uv <= 0.0) return 1.0f;
+  const double q = (u * u * kp.kmaj + v * v * kp.kmin) / uv;
+  return exp2_neg(d2 * q);
+}
+
+// ---------------------------------------------------------------- launchers
+// All launches are asynchronous on `st`; return hipSuccess or the launch error.
+
+hipError_t launch_prep(const double* lon, const double* lat, int64_t n, int64_t nside,
+                       uint32_t* keys, uint32_t* vals, int* flag, hipStream_t st);
+hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                      uint32_t* hist, int64_t n, int bits, bool* result_in_tmp, hipStream_t st);
+size_t radix_hist_elems(int64_t n);
+hipError_t launch_ring_offsets(const uint32_t* keys, int64_t n, int64_t nside, uint32_t* ring_off,
+                               hipStream_t st);
+hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int64_t n,
+                          const double* lon, const double* lat, const void* data, int dtype,
+                          int64_t ld, int64_t nchan, bool with_data, int64_t cap, double* sx,
+                          float* sdata, hipStream_t st);
+hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st);
+
+hipError_t launch_wcs_targets(const WcsDev& w, int64_t tile_w, int64_t tile_h, int64_t ntx,
+                              int64_t nslots, double* txyz, double* tll, int32_t* slot_target,
+                              int32_t* target_slot, hipStream_t st);
+hipError_t launch_sl_keys(const double* lon, const double* lat, int64_t n, uint32_t* keys,
+                          uint32_t* vals, int* flag, hipStream_t st);
+hipError_t launch_sl_targets(const double* lon, const double* lat, const uint32_t* order,
+                             int64_t ntarget, int64_t nslots, double* txyz, double* tll,
+                             int32_t* slot_target, int32_t* target_slot, hipStream_t st);
+hipError_t launch_tile_caps(const double* txyz, int64_t nslots, int64_t ntiles, double* caps,
+                            hipStream_t st);
+hipError_t launch_tile_span(const double* caps, int64_t ntiles, int64_t nside, double rho_extra,
+                            int32_t* ring_first, uint64_t* span_bound, hipStream_t st);
+hipError_t launch_tile_ranges(const double* caps, int64_t ntiles, int64_t nside, double rho_extra,
+                              const int32_t* ring_first, const uint64_t* range_off,
+                              const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
+                              uint32_t* nranges, uint64_t* ncand, hipStream_t st);
+hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
+                         const uint64_t* cand_off, int64_t ntiles, uint32_t* cand, hipStream_t st);
+
+// contraction kernels
+enum AccMode { ACC_OVERWRITE = 0, ACC_ADD = 1, ACC_FINAL = 2 };
+struct OutView {
+  float* S;            // [nchan][nslots] accumulator (ACC_OVERWRITE / ACC_ADD)
+  double* W;           // [nslots]
+  float* cube;         // ACC_FINAL: normalised output in user layout
+  float* wout;         // ACC_FINAL: weights in user layout (may be null)
+  const int32_t* slot_target;
+  int64_t ntarget;
+  int mode;
+};
+hipError_t launch_gather_fp32(const TileView& tv, const KernelParams& kp, int64_t ntiles,
+                              const uint32_t* vals, const void* data, int dtype, int64_t ld,
+                              const float* sdata, int64_t nchan, const OutView& ov, hipStream_t st);
+hipError_t launch_gather_mfma(const TileView& tv, const KernelParams& kp, int64_t ntiles,
+                              const uint32_t* vals, const void* data, int dtype, int64_t ld,
+                              int64_t nchan, int prec, const OutView& ov, hipStream_t st);
+bool mfma_available();
+hipError_t launch_stats(const TileView& tv, const KernelParams& kp, int64_t ntiles,
+                        const uint32_t* vals, const int32_t* slot_target, int32_t* counts,
+                        uint64_t* hashes, hipStream_t st);
+hipError_t launch_normalize(const float* S, const double* W, const int32_t* target_slot,
+                            int64_t nslots, int64_t nchan, int64_t ntarget, float* cube,
+                            float* wout, hipStream_t st);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
+
+}  // namespace cg

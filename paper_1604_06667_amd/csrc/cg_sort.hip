@@ -1,0 +1,309 @@
+// Sample preparation, device radix sort and HEALPix ring offsets.
+//
+// Sect. 2.2 step 3a / Sect. 3.4 (1): every input sample gets its HEALPix
+// index.  Sect. 3.4 inverts the sample -> target mapping into a target ->
+// sample mapping; here the inversion is a stable sort of the samples by
+// RING index, after which the samples of any pixel range of a ring form one
+// contiguous run that two binary searches find.
+#include "cg_internal.hpp"
+
+namespace cg {
+
+// ---------------------------------------------------------------------------
+// prep: RING key per sample; invalid coordinates get the sentinel key Npix
+// (sorted past every ring) and raise the sticky input flag.
+
+__global__ void __launch_bounds__(256) k_prep(const double* __restrict__ lon,
+                                              const double* __restrict__ lat, int64_t n,
+                                              int64_t nside, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = lon[i];
+  const double d = lat[i];
+  uint32_t key;
+  if (!(isfinite(a) && isfinite(d) && fabs(d) <= 90.0)) {
+    key = (uint32_t)hpx::npix(nside);
+    atomicOr(flag, 1);
+  } else {
+    double am = fmod(a, 360.0);
+    if (am < 0.0) am += 360.0;
+    const double phi = am * (hpx::kPi / 180.0);
+    double sd, cd;
+    sincos(d * (hpx::kPi / 180.0), &sd, &cd);
+    key = (uint32_t)hpx::ang2pix_ring(nside, sd, cd, phi);
+  }
+  keys[i] = key;
+  vals[i] = (uint32_t)i;
+}
+
+hipError_t launch_prep(const double* lon, const double* lat, int64_t n, int64_t nside,
+                       uint32_t* keys, uint32_t* vals, int* flag, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, st, lon, lat, n, nside, keys,
+                     vals, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort of (key, value) uint32 pairs, 8-bit digits.
+// Per pass: block histograms (digit-major), one exclusive scan, and a
+// stable scatter that ranks keys inside each wavefront with ballots.
+
+__global__ void __launch_bounds__(kSortThreads) k_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                       int shift, uint32_t* __restrict__ hist,
+                                                       int64_t nblocks) {
+  __shared__ uint32_t h[256];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + (int64_t)r * kSortThreads + t;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
+}
+
+// Single-workgroup exclusive scan (in place) of a uint32 array.
+__global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ a, int64_t n) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = (int64_t)t * per;
+  const int64_t e = b + per < n ? b + per : n;
+  uint32_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += a[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = (t >= off) ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+  for (int64_t i = b; i < e; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
+    const uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout) {
+  constexpr int NW = kSortThreads / 64;
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[NW][256];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  base[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t blk = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = blk + (int64_t)r * kSortThreads + t;
+    const bool valid = i < n;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    // lanes holding the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    for (int k = t; k < NW * 256; k += kSortThreads) (&wcnt[0][0])[k] = 0u;
+    __syncthreads();
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    {
+      // digit t: exclusive prefix over wavefronts on top of the running base
+      uint32_t run = base[t];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        const uint32_t c = wcnt[q][t];
+        wcnt[q][t] = run;
+        run += c;
+      }
+      base[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = wcnt[w][d] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+size_t radix_hist_elems(int64_t n) {
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  return (size_t)(nb < 1 ? 1 : nb) * 256;
+}
+
+hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                      uint32_t* hist, int64_t n, int bits, bool* result_in_tmp, hipStream_t st) {
+  *result_in_tmp = false;
+  if (n <= 1) return hipSuccess;
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  uint32_t *ki = keys, *vi = vals, *ko = keys_tmp, *vo = vals_tmp;
+  bool in_tmp = false;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, n, shift, hist,
+                       nb);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, hist, nb * 256);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, vi, n, shift,
+                       hist, nb, ko, vo);
+    uint32_t* tk = ki; ki = ko; ko = tk;
+    uint32_t* tv = vi; vi = vo; vo = tv;
+    in_tmp = !in_tmp;
+  }
+  *result_in_tmp = in_tmp;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ring_off[i] = first sorted position whose key is >= ring_start(i), for
+// i = 1 .. 4 nside; ring_off[4 nside] is the number of valid samples.
+
+__global__ void __launch_bounds__(256) k_ring_offsets(const uint32_t* __restrict__ keys, int64_t n,
+                                                      int64_t nside, uint32_t* __restrict__ ring_off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+  if (i > 4 * nside) return;
+  const uint64_t target = (uint64_t)hpx::ring_start(nside, i);
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((uint64_t)keys[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  ring_off[i] = (uint32_t)lo;
+  if (i == 1) ring_off[0] = 0;
+}
+
+hipError_t launch_ring_offsets(const uint32_t* keys, int64_t n, int64_t nside, uint32_t* ring_off,
+                               hipStream_t st) {
+  const int64_t cnt = 4 * nside;
+  hipLaunchKernelGGL(k_ring_offsets, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, keys, n,
+                     nside, ring_off);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// permute: sorted unit vectors (SoA) and, for narrow cubes, the data rows in
+// sorted order converted to FP32 (so the gather streams contiguous rows).
+
+template <typename T>
+__device__ __forceinline__ float to_f32(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ float to_f32<double>(const double* p, int64_t i) { return (float)p[i]; }
+template <>
+__device__ __forceinline__ float to_f32<float>(const float* p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float to_f32<uint16_t>(const uint16_t* p, int64_t i) {
+  return __uint_as_float(((uint32_t)p[i]) << 16);   // bfloat16 -> float (exact)
+}
+template <>
+__device__ __forceinline__ float to_f32<_Float16>(const _Float16* p, int64_t i) { return (float)p[i]; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute(const uint32_t* __restrict__ vals,
+                                                 const uint32_t* __restrict__ nvalid_p,
+                                                 const double* __restrict__ lon,
+                                                 const double* __restrict__ lat,
+                                                 const T* __restrict__ data, int64_t ld,
+                                                 int64_t nchan, int with_data, int64_t cap,
+                                                 double* __restrict__ sx, float* __restrict__ sdata) {
+  const int64_t nvalid = (int64_t)(*nvalid_p);
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nvalid) return;
+  const int64_t src = vals[p];
+  double am = fmod(lon[src], 360.0);
+  if (am < 0.0) am += 360.0;
+  double sa, ca, sd, cd;
+  sincos(am * (hpx::kPi / 180.0), &sa, &ca);
+  sincos(lat[src] * (hpx::kPi / 180.0), &sd, &cd);
+  sx[p] = cd * ca;
+  sx[cap + p] = cd * sa;
+  sx[2 * cap + p] = sd;
+  if (with_data) {
+    for (int64_t c = 0; c < nchan; ++c) sdata[p * nchan + c] = to_f32<T>(data, src * ld + c);
+  }
+}
+
+hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int64_t n,
+                          const double* lon, const double* lat, const void* data, int dtype,
+                          int64_t ld, int64_t nchan, bool with_data, int64_t cap, double* sx,
+                          float* sdata, hipStream_t st) {
+  // nvalid_dev points at the number of valid samples (ring_off[4 nside]);
+  // the grid covers all n sorted entries and threads past it return.
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+  const int wd = with_data ? 1 : 0;
+  switch (dtype) {
+    case 0:
+      hipLaunchKernelGGL(k_permute<double>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+                         (const double*)data, ld, nchan, wd, cap, sx, sdata);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_permute<float>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+                         (const float*)data, ld, nchan, wd, cap, sx, sdata);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_permute<_Float16>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+                         (const _Float16*)data, ld, nchan, wd, cap, sx, sdata);
+      break;
+    default:
+      hipLaunchKernelGGL(k_permute<uint16_t>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+                         (const uint16_t*)data, ld, nchan, wd, cap, sx, sdata);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of uint64 counts (tile candidate offsets); out has n + 1
+// entries, out[n] = total.
+
+__global__ void __launch_bounds__(1024) k_scan_u64(const uint64_t* __restrict__ in,
+                                                   uint64_t* __restrict__ out, int64_t n) {
+  __shared__ uint64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = (int64_t)t * per;
+  const int64_t e = b + per < n ? b + per : n;
+  uint64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += in[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint64_t v = (t >= off) ? part[t - off] : 0ull;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint64_t run = part[t] - s;
+  for (int64_t i = b; i < e; ++i) {
+    const uint64_t v = in[i];
+    out[i] = run;
+    run += v;
+  }
+  if (t == 1023) out[n] = part[1023];
+}
+
+hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_u64, dim3(1), dim3(1024), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace cg

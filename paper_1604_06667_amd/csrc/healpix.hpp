@@ -1,0 +1,284 @@
+// HEALPix RING-scheme geometry used for the sample lookup table.
+//
+// The paper grids through an internal HEALPix grid (Sect. 2.2) and
+// re-implements the HEALPix functions it needs (Sect. 3.2); the geometry
+// below is written from the definitions in Gorski et al. (2005), the
+// reference the paper cites for HEALPix:
+//
+//   * Npix = 12 nside^2 pixels in 4 nside - 1 iso-latitude rings.
+//   * North polar cap, ring i < nside: 4 i pixels, centres at
+//     z = 1 - i^2 / (3 nside^2), phi = (j + 1/2) pi / (2 i); first index 2 i (i - 1).
+//   * Equatorial belt, nside <= i <= 3 nside: 4 nside pixels, centres at
+//     z = 4/3 - 2 i / (3 nside), phi = (j + s/2) pi / (2 nside) with
+//     s = 1 when i - nside is even and s = 0 otherwise;
+//     first index 2 nside (nside - 1) + 4 nside (i - nside).
+//   * South cap mirrors the north cap.
+//
+// Everything here is __host__ __device__ so that the CPU tests exercise the
+// very code the kernels run.  FP64 throughout.
+#pragma once
+
+#include <stdint.h>
+#include <math.h>
+
+#ifdef __HIPCC__
+#define CG_HD __host__ __device__ inline
+#else
+#define CG_HD inline
+#endif
+
+namespace cg {
+namespace hpx {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+constexpr double kHalfPi = 1.57079632679489661923;
+
+CG_HD int64_t npix(int64_t nside) { return 12 * nside * nside; }
+CG_HD int64_t nrings(int64_t nside) { return 4 * nside - 1; }
+
+// Number of pixels in ring i (1 <= i <= 4 nside - 1).
+CG_HD int64_t ring_npix(int64_t nside, int64_t i) {
+  if (i < nside) return 4 * i;
+  if (i <= 3 * nside) return 4 * nside;
+  return 4 * (4 * nside - i);
+}
+
+// First RING index of ring i; ring_start(4 nside) = Npix is the end sentinel.
+CG_HD int64_t ring_start(int64_t nside, int64_t i) {
+  if (i <= nside) return 2 * i * (i - 1);
+  if (i <= 3 * nside) return 2 * nside * (nside - 1) + 4 * nside * (i - nside);
+  const int64_t ip = 4 * nside - i;
+  return 12 * nside * nside - 2 * ip * (ip + 1);
+}
+
+// z of the centre of ring i; z(0) = 1 and z(4 nside) = -1 close the range.
+CG_HD double ring_z(int64_t nside, int64_t i) {
+  if (i <= 0) return 1.0;
+  if (i >= 4 * nside) return -1.0;
+  const double ns = (double)nside;
+  if (i < nside) return 1.0 - (double)(i * i) / (3.0 * ns * ns);
+  if (i <= 3 * nside) return 4.0 / 3.0 - 2.0 * (double)i / (3.0 * ns);
+  const int64_t ip = 4 * nside - i;
+  return -(1.0 - (double)(ip * ip) / (3.0 * ns * ns));
+}
+
+// Continuous ring coordinate of a latitude: the ring whose centre has this z
+// (inverse of ring_z, monotone decreasing in z).
+CG_HD double ring_of_z(int64_t nside, double z) {
+  const double ns = (double)nside;
+  if (z > 2.0 / 3.0) return ns * sqrt(3.0 * (1.0 - z));
+  if (z < -2.0 / 3.0) return 4.0 * ns - ns * sqrt(3.0 * (1.0 + z));
+  return ns * (2.0 - 1.5 * z);
+}
+
+// Angle -> RING index.  z = cos(theta) = sin(lat), st = sin(theta) = cos(lat)
+// (passed separately so that near the poles 1 - |z| is not formed by
+// cancellation), phi in [0, 2 pi).
+CG_HD int64_t ang2pix_ring(int64_t nside, double z, double st, double phi) {
+  const double za = fabs(z);
+  double tt = phi * (2.0 / kPi);          // [0, 4)
+  if (tt >= 4.0) tt -= 4.0;
+  if (tt < 0.0) tt += 4.0;
+  if (za <= 2.0 / 3.0) {
+    const double t1 = (double)nside * (0.5 + tt);
+    const double t2 = (double)nside * z * 0.75;
+    const int64_t jp = (int64_t)floor(t1 - t2);   // index of the ascending edge line
+    const int64_t jm = (int64_t)floor(t1 + t2);   // index of the descending edge line
+    const int64_t ir = nside + 1 + jp - jm;       // ring counted from z = 2/3, 1..2 nside + 1
+    const int64_t kshift = 1 - (ir & 1);
+    int64_t ip = (jp + jm - nside + kshift + 1) / 2;
+    const int64_t nl4 = 4 * nside;
+    ip %= nl4;
+    if (ip < 0) ip += nl4;
+    return 2 * nside * (nside - 1) + (ir - 1) * nl4 + ip;
+  }
+  const double tp = tt - floor(tt);
+  const double tmp = (double)nside * st * sqrt(3.0 / (1.0 + za));   // nside sqrt(3 (1 - |z|))
+  const int64_t jp = (int64_t)(tp * tmp);
+  const int64_t jm = (int64_t)((1.0 - tp) * tmp);
+  int64_t ir = jp + jm + 1;                        // ring counted from the nearer pole
+  if (ir > nside) ir = nside;
+  int64_t ip = (int64_t)(tt * (double)ir);
+  ip %= 4 * ir;
+  if (ip < 0) ip += 4 * ir;
+  if (z > 0.0) return 2 * ir * (ir - 1) + ip;
+  return 12 * nside * nside - 2 * ir * (ir + 1) + ip;
+}
+
+CG_HD int64_t isqrt64(int64_t v) {
+  int64_t r = (int64_t)sqrt((double)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+// RING index -> (ring i, position j in ring).
+CG_HD void pix2ring(int64_t nside, int64_t p, int64_t* ring, int64_t* j) {
+  const int64_t ncap = 2 * nside * (nside - 1);
+  const int64_t np = 12 * nside * nside;
+  if (p < ncap) {
+    int64_t i = (1 + isqrt64(1 + 2 * p)) / 2;
+    while (2 * i * (i - 1) > p) --i;
+    while (2 * (i + 1) * i <= p) ++i;
+    *ring = i;
+    *j = p - 2 * i * (i - 1);
+  } else if (p < np - ncap) {
+    const int64_t q = p - ncap;
+    *ring = q / (4 * nside) + nside;
+    *j = q % (4 * nside);
+  } else {
+    const int64_t q = np - p;                       // 1 .. ncap
+    int64_t ip = (1 + isqrt64(2 * q - 1)) / 2;      // ring counted from the south pole
+    while (2 * ip * (ip - 1) >= q) --ip;
+    while (2 * ip * (ip + 1) < q) ++ip;
+    *ring = 4 * nside - ip;
+    *j = p - (np - 2 * ip * (ip + 1));
+  }
+}
+
+// Centre of RING pixel p: z and phi.
+CG_HD void pix2ang_ring(int64_t nside, int64_t p, double* z, double* phi) {
+  int64_t i, j;
+  pix2ring(nside, p, &i, &j);
+  *z = ring_z(nside, i);
+  double shift;
+  int64_t n;
+  if (i < nside) { n = 4 * i; shift = 0.5; }
+  else if (i <= 3 * nside) { n = 4 * nside; shift = ((i - nside) & 1) ? 0.0 : 0.5; }
+  else { n = 4 * (4 * nside - i); shift = 0.5; }
+  *phi = ((double)j + shift) * kTwoPi / (double)n;
+}
+
+// ---------------------------------------------------------------------------
+// Ring lookup for a spherical cap (the target-centric form of the paper's
+// per-ring disk query shifted in longitude, Sect. 3.3 Eq. 4-5).
+//
+// For ring i, returns up to two inclusive RING-index ranges that contain
+// every pixel of ring i holding a point within angular radius rho of the
+// cap centre (cz = cos theta_c, cs = sin theta_c, cphi).  Properties used:
+//   * a point whose pixel lies in ring i has z in [z(i+1), z(i-1)];
+//   * within ring i, pixel j covers longitudes inside
+//     [(j - 1/2), (j + 1)] * 2 pi / n_i (cap pixels: exactly [j, j+1));
+//   * over a latitude band the half-width in longitude of the cap,
+//     dphi(z) = acos((cos rho - z cz) / (sqrt(1 - z^2) cs)), is largest at
+//     z* = cz / cos rho, so its maximum over [a, b] is dphi(clamp(z*, a, b)).
+// One pixel of slack is added on each side.  Returns the number of ranges.
+CG_HD int ring_cap_ranges(int64_t nside, int64_t i, double cz, double cs, double cphi,
+                          double rho, int64_t lo[2], int64_t hi[2]) {
+  const int64_t n = ring_npix(nside, i);
+  const int64_t s0 = ring_start(nside, i);
+  // latitude band of the cap (pole-containing caps reach z = +-1)
+  const double thc = atan2(cs, cz);
+  const double zmax = (thc - rho <= 0.0) ? 1.0 : cos(thc - rho);
+  const double zmin = (thc + rho >= kPi) ? -1.0 : cos(thc + rho);
+  const double eps = 1e-12;
+  const double zl = ring_z(nside, i + 1) - eps;
+  const double zh = ring_z(nside, i - 1) + eps;
+  const double a = zl > zmin ? zl : zmin;
+  const double b = zh < zmax ? zh : zmax;
+  if (a > b) return 0;
+  bool full = (rho >= kHalfPi);
+  double dphi = kPi;
+  if (!full) {
+    const double crho = cos(rho);
+    double zs = cz / crho;
+    zs = zs < a ? a : (zs > b ? b : zs);
+    const double sz = sqrt(fmax(0.0, (1.0 - zs) * (1.0 + zs)));
+    const double den = sz * cs;
+    if (den <= 0.0) {
+      full = true;
+    } else {
+      const double arg = (crho - zs * cz) / den;
+      if (arg <= -1.0) full = true;
+      else dphi = (arg >= 1.0) ? 0.0 : acos(arg);
+    }
+  }
+  if (!full) {
+    const double scale = (double)n / kTwoPi;
+    int64_t jl = (int64_t)floor((cphi - dphi) * scale) - 1;
+    int64_t jh = (int64_t)floor((cphi + dphi) * scale) + 1;
+    if (jh - jl + 1 >= n) {
+      full = true;
+    } else if (jl < 0) {
+      if (jh < 0) { lo[0] = s0 + jl + n; hi[0] = s0 + jh + n; return 1; }
+      lo[0] = s0; hi[0] = s0 + jh;
+      lo[1] = s0 + jl + n; hi[1] = s0 + n - 1;
+      return 2;
+    } else if (jh >= n) {
+      if (jl >= n) { lo[0] = s0 + jl - n; hi[0] = s0 + jh - n; return 1; }
+      lo[0] = s0; hi[0] = s0 + jh - n;
+      lo[1] = s0 + jl; hi[1] = s0 + n - 1;
+      return 2;
+    } else {
+      lo[0] = s0 + jl; hi[0] = s0 + jh;
+      return 1;
+    }
+  }
+  lo[0] = s0; hi[0] = s0 + n - 1;
+  return 1;
+}
+
+// Rings whose pixels can meet a cap of radius rho around colatitude thc:
+// [first, last], clamped to [1, 4 nside - 1].  Conservative by two rings.
+CG_HD void cap_ring_span(int64_t nside, double cz, double cs, double rho,
+                         int64_t* first, int64_t* last) {
+  const double thc = atan2(cs, cz);
+  const double zmax = (thc - rho <= 0.0) ? 1.0 : cos(thc - rho);
+  const double zmin = (thc + rho >= kPi) ? -1.0 : cos(thc + rho);
+  int64_t f = (int64_t)floor(ring_of_z(nside, zmax)) - 2;
+  int64_t l = (int64_t)ceil(ring_of_z(nside, zmin)) + 2;
+  if (f < 1) f = 1;
+  if (l > 4 * nside - 1) l = 4 * nside - 1;
+  *first = f;
+  *last = l;
+}
+
+// Angle -> NESTED index (Gorski et al. 2005): used only to order sight-line
+// targets along a space-filling curve so that runs of consecutive targets
+// are compact.  nside must be a power of two.
+CG_HD uint64_t spread_bits(uint64_t v) {
+  v &= 0xFFFFFFFFull;
+  v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+  v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+  v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  v = (v | (v << 2)) & 0x3333333333333333ull;
+  v = (v | (v << 1)) & 0x5555555555555555ull;
+  return v;
+}
+
+CG_HD int64_t ang2pix_nest(int64_t nside, double z, double st, double phi) {
+  const double za = fabs(z);
+  double tt = phi * (2.0 / kPi);
+  if (tt >= 4.0) tt -= 4.0;
+  if (tt < 0.0) tt += 4.0;
+  int64_t face, ix, iy;
+  if (za <= 2.0 / 3.0) {
+    const double t1 = (double)nside * (0.5 + tt);
+    const double t2 = (double)nside * z * 0.75;
+    const int64_t jp = (int64_t)floor(t1 - t2);
+    const int64_t jm = (int64_t)floor(t1 + t2);
+    const int64_t ifp = jp / nside;
+    const int64_t ifm = jm / nside;
+    if (ifp == ifm) face = (ifp & 3) | 4;
+    else if (ifp < ifm) face = ifp & 3;
+    else face = (ifm & 3) + 8;
+    ix = jm & (nside - 1);
+    iy = nside - (jp & (nside - 1)) - 1;
+  } else {
+    int64_t ntt = (int64_t)tt;
+    if (ntt > 3) ntt = 3;
+    const double tp = tt - (double)ntt;
+    const double tmp = (double)nside * st * sqrt(3.0 / (1.0 + za));
+    int64_t jp = (int64_t)(tp * tmp);
+    int64_t jm = (int64_t)((1.0 - tp) * tmp);
+    if (jp > nside - 1) jp = nside - 1;
+    if (jm > nside - 1) jm = nside - 1;
+    if (z >= 0) { face = ntt; ix = nside - jm - 1; iy = nside - jp - 1; }
+    else { face = ntt + 8; ix = jp; iy = jm; }
+  }
+  return face * nside * nside + (int64_t)(spread_bits((uint64_t)ix) | (spread_bits((uint64_t)iy) << 1));
+}
+
+}  // namespace hpx
+}  // namespace cg

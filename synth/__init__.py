@@ -308,7 +308,7 @@ def config3(nsamples: int = 12_000_000, naxis1: int = 4320, nchan: int = 8,
     return Workload(f"C3 all-sky {nsamples} x {naxis1}x{naxis2} CAR x {nchan}ch",
                     lon, lat, data, "f32", {"kind": "wcs", "wcs": wcs},
                     ("gauss1d", (sigma,)), 3.0 * sigma,
-                    nside=max(16, int(1024 * naxis1 // 4320)))
+                    nside=max(16, 1 << int(math.floor(math.log2(1024 * naxis1 / 4320)))))
 
 
 def config4(njobs: int = 64, scale: float = 1.0, device="cpu") -> list[Workload]:

@@ -1,0 +1,92 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1604_06667_amd as cgp
+from paper_1604_06667_amd import _cg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "cg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    L = cgp.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_cg.SIGNATURES), "binding and header disagree"
+    assert "gfx950" in cgp.version()
+
+
+def test_host_argument_errors():
+    L = cgp.lib()
+    h = C.c_void_p()
+    assert L.cg_create_wcs(None, None, 1) == _cg.E_INVALID
+    w = _cg.CgWcs(7, 0, 10, 10, 1, 1, 0, 0, 1, 1)
+    assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_UNSUPPORTED
+    w = _cg.CgWcs(0, 0, 0, 10, 1, 1, 0, 0, 1, 1)
+    assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_INVALID
+    w = _cg.CgWcs(0, 0, 10, 10, 1, 1, 0, 0, 1, 1)
+    assert L.cg_create_wcs(C.byref(h), C.byref(w), 0) == _cg.E_INVALID
+    w = _cg.CgWcs(0, 0, 10, 10, 1, 1, 0, 5.0, 1, 1)      # oblique CAR
+    assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_UNSUPPORTED
+    assert "oblique" in L.cg_last_error().decode()
+    w = _cg.CgWcs(1, 0, 10, 10, 1, 1, 0, 0, 0.0, 1)      # zero CDELT
+    assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_INVALID
+    assert L.cg_create_sightlines(C.byref(h), None, None, 5, 1, None) == _cg.E_INVALID
+    p = (C.c_double * 1)(1.0)
+    assert L.cg_set_kernel(None, 0, p, 1, 1.0, 1.0) == _cg.E_INVALID
+    assert L.cg_grid(None, None, None, None, 1, 1, 1, None) == _cg.E_INVALID
+    assert L.cg_set_nside(None, 64) == _cg.E_INVALID
+    assert L.cg_sync(None, None) == _cg.E_INVALID
+    v = C.c_int64()
+    assert L.cg_query(None, 0, C.byref(v)) == _cg.E_INVALID
+    with pytest.raises(cgp.CgError):
+        cgp.hpx_ang2pix_ring(0, [0.0], [0.0])
+    with pytest.raises(cgp.CgError):
+        cgp.hpx_cap_ranges(64, 0, 0, 30.0, max_ranges=2)
+    with pytest.raises(cgp.CgError):
+        cgp.wcs_pix2world({"NAXIS1": 4, "NAXIS2": 4, "CTYPE1": "RA---TAN", "CDELT1": 1, "CDELT2": 1},
+                          [1.0], [1.0])
+
+
+@pytest.mark.parametrize("hdr", [
+    {"NAXIS": 2, "NAXIS1": 96, "NAXIS2": 96, "CTYPE1": "RA---CAR", "CTYPE2": "DEC--CAR",
+     "CRPIX1": 48.5, "CRPIX2": -851.5, "CRVAL1": 120.0, "CRVAL2": 0.0,
+     "CDELT1": -1 / 30, "CDELT2": 1 / 30},
+    {"NAXIS": 2, "NAXIS1": 600, "NAXIS2": 600, "CTYPE1": "RA---SIN", "CTYPE2": "DEC--SIN",
+     "CRPIX1": 300.5, "CRPIX2": 300.5, "CRVAL1": 120.0, "CRVAL2": 30.0,
+     "CDELT1": -1 / 60, "CDELT2": 1 / 60},
+    {"NAXIS": 2, "NAXIS1": 101, "NAXIS2": 101, "CTYPE1": "GLON-SIN", "CTYPE2": "GLAT-SIN",
+     "CRPIX1": 51, "CRPIX2": 51, "CRVAL1": 12.345, "CRVAL2": 87.0, "CDELT1": -1.0, "CDELT2": 1.0},
+    {"NAXIS": 2, "NAXIS1": 4320, "NAXIS2": 2160, "CTYPE1": "RA---CAR", "CTYPE2": "DEC--CAR",
+     "CRPIX1": 2160.5, "CRPIX2": 1080.5, "CRVAL1": 0.0, "CRVAL2": 0.0,
+     "CDELT1": -1 / 12, "CDELT2": 1 / 12},
+])
+def test_library_wcs_matches_oracle(hdr):
+    g = np.random.default_rng(0)
+    n = 5000
+    i = g.uniform(0.5, hdr["NAXIS1"] + 0.5, n)
+    j = g.uniform(0.5, hdr["NAXIS2"] + 0.5, n)
+    lo, la = cgp.wcs_pix2world(hdr, i, j)
+    w = {"proj": hdr["CTYPE1"][-3:], "naxis1": hdr["NAXIS1"], "naxis2": hdr["NAXIS2"],
+         "crpix1": hdr["CRPIX1"], "crpix2": hdr["CRPIX2"], "crval1": hdr["CRVAL1"],
+         "crval2": hdr["CRVAL2"], "cdelt1": hdr["CDELT1"], "cdelt2": hdr["CDELT2"]}
+    olo, ola = oracle.wcs_world(w, i, j)
+    assert np.array_equal(np.isnan(lo), np.isnan(olo))
+    ok = ~np.isnan(lo)
+    np.testing.assert_allclose(la[ok], ola[ok], atol=1e-10)
+    dl = (lo[ok] - olo[ok] + 180.0) % 360.0 - 180.0
+    assert np.abs(dl * np.cos(np.radians(ola[ok]))).max() < 1e-10

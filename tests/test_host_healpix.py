@@ -1,0 +1,134 @@
+"""Host build of the library's HEALPix RING code (the code the kernels run).
+
+Pinned to the definitions of Gorski et al. (2005), cited by the paper for
+the HEALPix grid (Sect. 2.2, 3.2): ring counts, start indices and centre
+latitudes in closed form, exact pix -> ang -> pix round trips, equal pixel
+areas, and the two geometric facts the ring lookup relies on (latitude
+extent of a ring, longitude extent of a pixel), then the lookup's superset
+property against brute-force distances.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_1604_06667_amd as cgp
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 64, 1024, 8192])
+def test_ring_table_closed_forms(nside):
+    total = 0
+    for i in [1, 2, nside - 1, nside, nside + 1, 2 * nside, 3 * nside, 3 * nside + 1, 4 * nside - 1]:
+        if i < 1 or i > 4 * nside - 1:
+            continue
+        s, n, z = cgp.hpx_ring_info(nside, i)
+        if i < nside:
+            assert n == 4 * i and s == 2 * i * (i - 1)
+            assert z == pytest.approx(1 - i * i / (3 * nside * nside), abs=1e-15)
+        elif i <= 3 * nside:
+            assert n == 4 * nside and s == 2 * nside * (nside - 1) + 4 * nside * (i - nside)
+            assert z == pytest.approx(4 / 3 - 2 * i / (3 * nside), abs=1e-15)
+        else:
+            k = 4 * nside - i
+            assert n == 4 * k and s == 12 * nside * nside - 2 * k * (k + 1)
+            assert z == pytest.approx(-(1 - k * k / (3 * nside * nside)), abs=1e-15)
+    if nside <= 64:
+        for i in range(1, 4 * nside):
+            s, n, _ = cgp.hpx_ring_info(nside, i)
+            assert s == total
+            total += n
+        assert total == 12 * nside * nside
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 16, 32, 64])
+def test_round_trip_every_pixel(nside):
+    pix = np.arange(12 * nside * nside)
+    lon, lat = cgp.hpx_pix2ang_ring(nside, pix)
+    assert np.array_equal(cgp.hpx_ang2pix_ring(nside, lon, lat), pix)
+    ring, j = cgp.hpx_pix2ring(nside, pix)
+    # pixel centres: ring centre z, evenly spaced longitudes with the belt shift
+    for i in np.unique(ring):
+        m = ring == i
+        s, n, z = cgp.hpx_ring_info(nside, int(i))
+        assert m.sum() == n
+        np.testing.assert_allclose(np.sin(np.radians(lat[m])), z, atol=1e-13)
+        shift = 0.5 if (i < nside or i > 3 * nside or (i - nside) % 2 == 0) else 0.0
+        np.testing.assert_allclose(lon[m], (j[m] + shift) * 360.0 / n, atol=1e-10)
+
+
+@pytest.mark.parametrize("nside", [4, 16])
+def test_equal_area(nside):
+    g = np.random.default_rng(nside)
+    n = 2_000_000
+    lon = g.uniform(0, 360, n)
+    lat = np.degrees(np.arcsin(g.uniform(-1, 1, n)))
+    pix = cgp.hpx_ang2pix_ring(nside, lon, lat)
+    cnt = np.bincount(pix, minlength=12 * nside * nside)
+    e = n / cnt.size
+    chi2 = ((cnt - e) ** 2 / e).sum()
+    dof = cnt.size - 1
+    assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof)
+
+
+def _random_points(g, n):
+    lon = g.uniform(0, 360, n)
+    lat = np.degrees(np.arcsin(g.uniform(-1, 1, n)))
+    return lon, lat
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 16, 256])
+def test_ring_latitude_and_pixel_longitude_extent(nside):
+    g = np.random.default_rng(100 + nside)
+    lon, lat = _random_points(g, 400_000)
+    # include the poles and points on ring-centre latitudes
+    lon = np.r_[lon, 17.0, 203.0]
+    lat = np.r_[lat, 90.0, -90.0]
+    pix = cgp.hpx_ang2pix_ring(nside, lon, lat)
+    ring, j = cgp.hpx_pix2ring(nside, pix)
+    zc = np.array([1.0] + [cgp.hpx_ring_info(nside, i)[2] for i in range(1, 4 * nside)] + [-1.0])
+    z = np.sin(np.radians(lat))
+    assert np.all(z <= zc[ring - 1] + 1e-12) and np.all(z >= zc[ring + 1] - 1e-12)
+    n = np.array([cgp.hpx_ring_info(nside, int(i))[1] for i in ring])
+    x = np.radians(lon) * n / (2 * math.pi)          # longitude in units of pixels
+    # pixel j covers longitudes within [j - 1/2, j + 1] (mod n)
+    d = (x - j + n / 2.0) % n - n / 2.0
+    assert np.all(d >= -0.5 - 1e-9) and np.all(d <= 1.0 + 1e-9)
+
+
+def _brute_pix_within(nside, lon0, lat0, rho, g, n=60_000):
+    """Pixels of random points inside the cap (rejection sampling near it)."""
+    c = np.array([math.cos(math.radians(lat0)) * math.cos(math.radians(lon0)),
+                  math.cos(math.radians(lat0)) * math.sin(math.radians(lon0)),
+                  math.sin(math.radians(lat0))])
+    zmin = math.cos(min(math.pi, math.radians(90 - lat0) + rho))
+    zmax = math.cos(max(0.0, math.radians(90 - lat0) - rho))
+    z = g.uniform(zmin, zmax, n)
+    lon = g.uniform(0, 360, n)
+    lat = np.degrees(np.arcsin(z))
+    p = np.stack([np.sqrt(1 - z * z) * np.cos(np.radians(lon)),
+                  np.sqrt(1 - z * z) * np.sin(np.radians(lon)), z], 1)
+    ang = np.arctan2(np.linalg.norm(np.cross(p, c), axis=1), p @ c)
+    m = ang <= rho
+    return cgp.hpx_ang2pix_ring(nside, lon[m], lat[m])
+
+
+CAPS = [(10.0, 20.0, 1.0), (0.05, -3.0, 0.5), (359.9, 41.0, 0.2), (123.0, 89.7, 0.5),
+        (250.0, -89.95, 0.1), (45.0, 0.0, 0.01), (300.0, 41.8, 2.0), (180.0, -41.8, 3.0),
+        (77.0, 60.0, 30.0), (5.0, 10.0, 100.0), (200.0, 90.0, 0.3), (33.0, -90.0, 1.0)]
+
+
+@pytest.mark.parametrize("nside", [1, 4, 64, 1024, 8192])
+@pytest.mark.parametrize("cap", CAPS, ids=lambda c: f"{c[0]}_{c[1]}_{c[2]}")
+def test_cap_ranges_superset(nside, cap):
+    lon0, lat0, rho_deg = cap
+    g = np.random.default_rng(int(nside + 7 * rho_deg * 100 + lat0 * 10) & 0xFFFF)
+    rng = cgp.hpx_cap_ranges(nside, lon0, lat0, rho_deg)
+    pix = _brute_pix_within(nside, lon0, lat0, math.radians(rho_deg), g)
+    assert pix.size > 0
+    lo, hi = rng[:, 0], rng[:, 1]
+    assert np.all(hi >= lo)
+    order = np.argsort(lo)
+    lo, hi = lo[order], hi[order]
+    k = np.searchsorted(lo, pix, side="right") - 1
+    inside = (k >= 0) & (pix <= hi[np.maximum(k, 0)])
+    assert inside.all(), f"{(~inside).sum()} pixels of in-cap points missed"
