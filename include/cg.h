@@ -66,8 +66,11 @@ typedef enum cg_dtype { CG_F64 = 0, CG_F32 = 1, CG_F16 = 2, CG_BF16 = 3 } cg_dty
  * test are FP64 and the weight map W is accumulated in FP64 in every mode */
 typedef enum cg_prec {
   CG_PREC_FP32 = 0,   /* FP32 weights x FP32 data on the vector ALUs, two-level FP64 sums */
-  CG_PREC_BF16 = 1,   /* BF16 weights x BF16 data on the matrix cores (MFMA), FP32 accumulate */
-  CG_PREC_FP16 = 2    /* FP16 weights x FP16 data on the matrix cores (MFMA), FP32 accumulate */
+  CG_PREC_BF16 = 1,   /* matrix cores (MFMA), BF16 operands, FP32 accumulate: data and weights
+                         are split into BF16 high and residual parts and each block is the sum
+                         of three products (hi*hi + lo*hi + hi*lo) */
+  CG_PREC_FP16 = 2    /* matrix cores (MFMA), one FP16 product per block, FP32 accumulate;
+                         data must lie within the FP16 range */
 } cg_prec;
 
 typedef enum cg_kernel_type {
@@ -180,6 +183,16 @@ cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double*
 /* Handle queries (host):  what = 0 ntargets, 1 nchan, 2 nside, 3 ntiles,
  * 4 candidates in the last grid call, 5 precision, 6 device. */
 cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value);
+
+/* Measurement: while enabled, every launch of the contraction kernel (the
+ * step that evaluates Eq. 1-2) made by this handle is bracketed by two HIP
+ * events recorded on the stream it is launched on; at most 4096 launches are
+ * kept after enabling.  enable = 0 stops recording.  Errors: CG_E_DEVICE. */
+cg_status cg_profile_enable(cg_gridder* g, int32_t enable);
+
+/* Number of bracketed contraction launches since the last enable and their
+ * summed duration in milliseconds.  Waits for the last recorded launch. */
+cg_status cg_profile_read(cg_gridder* g, int64_t* launches, double* total_ms);
 
 void cg_destroy(cg_gridder* g);
 const char* cg_last_error(void);

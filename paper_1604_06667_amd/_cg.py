@@ -51,6 +51,8 @@ SIGNATURES = {
     "cg_sync": (_i32, [_vp, _vp]),
     "cg_neighbour_stats": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "cg_query": (_i32, [_vp, _i32, _P(_i64)]),
+    "cg_profile_enable": (_i32, [_vp, _i32]),
+    "cg_profile_read": (_i32, [_vp, _P(_i64), _P(_d)]),
     "cg_destroy": (None, [_vp]),
     "cg_last_error": (C.c_char_p, []),
     "cg_version": (C.c_char_p, []),
@@ -257,6 +259,14 @@ class _Gridder:
         v = C.c_int64()
         check(lib().cg_query(self._handle(), int(what), C.byref(v)))
         return v.value
+
+    def profile(self, enable=True):
+        check(lib().cg_profile_enable(self._handle(), 1 if enable else 0))
+
+    def profile_read(self):
+        n, ms = C.c_int64(), C.c_double()
+        check(lib().cg_profile_read(self._handle(), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
     @property
     def nside(self):

@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/cg.h"
 #include "cg_internal.hpp"
@@ -90,7 +92,7 @@ struct cg_gridder {
   bool span_valid = false;
   DevBuf ring_first, span_bound, range_off;
   int64_t total_ranges = 0;
-  DevBuf S, W;
+  DevBuf S, W, Wn;
   bool fresh = true;
   DevBuf flag;
   DevBuf keys, vals, keys2, vals2, hist, ring_off, sx, sdata, ranges, nranges, ncand, cand_off,
@@ -100,6 +102,9 @@ struct cg_gridder {
   int64_t last_n = 0;
   int64_t last_ncand = 0;
   uint64_t* h_word = nullptr;  // pinned host word
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t nev = 0;
 };
 
 namespace {
@@ -117,6 +122,7 @@ cg_status alloc_targets(cg_gridder* g) {
          "alloc targets");
   CG_HIP(ensure(g->caps, sizeof(double) * 4 * (g->ntiles > 0 ? g->ntiles : 1)), "alloc caps");
   CG_HIP(ensure(g->W, sizeof(double) * g->nslots), "alloc weights");
+  CG_HIP(ensure(g->Wn, sizeof(double) * g->nslots), "alloc weights");
   CG_HIP(ensure(g->flag, sizeof(int)), "alloc flag");
   CG_HIP(hipMemset(g->flag.p, 0, sizeof(int)), "clear flag");
   CG_HIP(hipHostMalloc((void**)&g->h_word, sizeof(uint64_t) * 2, hipHostMallocDefault),
@@ -231,9 +237,22 @@ cg_status check_grid_args(const cg_gridder* g, const double* lon, const double* 
   return CG_OK;
 }
 
+constexpr size_t kMaxProfiled = 4096;
+
 cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
                    const cg::OutView& ov, hipStream_t st) {
   const cg::TileView tv = tile_view(g);
+  std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
+  if (g->prof && g->nev < kMaxProfiled) {
+    if (g->nev == g->ev.size()) {
+      hipEvent_t a, b;
+      CG_HIP(hipEventCreate(&a), "event");
+      CG_HIP(hipEventCreate(&b), "event");
+      g->ev.emplace_back(a, b);
+    }
+    pe = &g->ev[g->nev++];
+    CG_HIP(hipEventRecord(pe->first, st), "event record");
+  }
   if (g->prec == CG_PREC_FP32) {
     CG_HIP(cg::launch_gather_fp32(tv, g->kp, g->ntiles, g->sorted_vals, data, dtype, ld,
                                   g->sdata.as<float>(), g->nchan, ov, st),
@@ -243,6 +262,7 @@ cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
                                   g->prec, ov, st),
            "gather (mfma)");
   }
+  if (pe) CG_HIP(hipEventRecord(pe->second, st), "event record");
   return CG_OK;
 }
 
@@ -436,6 +456,7 @@ cg_status cg_grid(cg_gridder* g, const double* lon_deg, const double* lat_deg, c
   cg::OutView ov{};
   ov.S = g->S.as<float>();
   ov.W = g->W.as<double>();
+  ov.Wn = g->Wn.as<double>();
   ov.slot_target = g->slot_target.as<int32_t>();
   ov.ntarget = g->ntarget;
   ov.mode = g->fresh ? cg::ACC_OVERWRITE : cg::ACC_ADD;
@@ -479,8 +500,9 @@ cg_status cg_get_datacube(cg_gridder* g, float* out, void* stream) {
     CG_HIP(cg::launch_fill(out, g->nchan * g->ntarget, __builtin_nanf(""), st), "fill");
     return CG_OK;
   }
-  CG_HIP(cg::launch_normalize(g->S.as<float>(), g->W.as<double>(), g->target_slot.as<int32_t>(),
-                              g->nslots, g->nchan, g->ntarget, out, nullptr, st),
+  CG_HIP(cg::launch_normalize(g->S.as<float>(), g->W.as<double>(), g->Wn.as<double>(),
+                              g->target_slot.as<int32_t>(), g->nslots, g->nchan, g->ntarget, out,
+                              nullptr, st),
          "normalize");
   return CG_OK;
 }
@@ -495,8 +517,9 @@ cg_status cg_get_weights(cg_gridder* g, float* out, void* stream) {
     CG_HIP(cg::launch_fill(out, g->ntarget, 0.0f, st), "fill");
     return CG_OK;
   }
-  CG_HIP(cg::launch_normalize(nullptr, g->W.as<double>(), g->target_slot.as<int32_t>(), g->nslots,
-                              g->nchan, g->ntarget, nullptr, out, st),
+  CG_HIP(cg::launch_normalize(nullptr, g->W.as<double>(), g->Wn.as<double>(),
+                              g->target_slot.as<int32_t>(), g->nslots, g->nchan, g->ntarget,
+                              nullptr, out, st),
          "weights");
   return CG_OK;
 }
@@ -563,11 +586,38 @@ cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value) {
   return CG_OK;
 }
 
+cg_status cg_profile_enable(cg_gridder* g, int32_t enable) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  g->prof = enable != 0;
+  if (g->prof) g->nev = 0;
+  return CG_OK;
+}
+
+cg_status cg_profile_read(cg_gridder* g, int64_t* launches, double* total_ms) {
+  if (!g || !launches || !total_ms) return fail(CG_E_INVALID, "null pointer");
+  cg_status s = set_dev(g);
+  if (s != CG_OK) return s;
+  double tot = 0.0;
+  for (size_t i = 0; i < g->nev; ++i) {
+    CG_HIP(hipEventSynchronize(g->ev[i].second), "event sync");
+    float ms = 0.0f;
+    CG_HIP(hipEventElapsedTime(&ms, g->ev[i].first, g->ev[i].second), "event time");
+    tot += ms;
+  }
+  *launches = (int64_t)g->nev;
+  *total_ms = tot;
+  return CG_OK;
+}
+
 void cg_destroy(cg_gridder* g) {
   if (!g) return;
   (void)hipSetDevice(g->device);
+  for (auto& e : g->ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   DevBuf* bufs[] = {&g->txyz, &g->tll, &g->slot_target, &g->target_slot, &g->caps,
-                    &g->ring_first, &g->span_bound, &g->range_off, &g->S, &g->W, &g->flag,
+                    &g->ring_first, &g->span_bound, &g->range_off, &g->S, &g->W, &g->Wn, &g->flag,
                     &g->keys, &g->vals, &g->keys2, &g->vals2, &g->hist, &g->ring_off, &g->sx,
                     &g->sdata, &g->ranges, &g->nranges, &g->ncand, &g->cand_off, &g->cand};
   for (DevBuf* b : bufs) b->release();

@@ -107,6 +107,7 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
       *s = add ? (float)((double)*s + acc[c]) : (float)acc[c];
     }
     ov.W[slot] = add ? ov.W[slot] + wacc : wacc;
+    ov.Wn[slot] = add ? ov.Wn[slot] + wacc : wacc;
   }
 }
 
@@ -294,6 +295,7 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
       if (tg >= 0 && ov.wout) ov.wout[tg] = (float)s_w[t];
     } else {
       ov.W[slot] = ov.mode == ACC_ADD ? ov.W[slot] + s_w[t] : s_w[t];
+      ov.Wn[slot] = ov.mode == ACC_ADD ? ov.Wn[slot] + s_w[t] : s_w[t];
     }
   }
 }
@@ -415,6 +417,7 @@ hipError_t launch_stats(const TileView& tv, const KernelParams& kp, int64_t ntil
 
 __global__ void __launch_bounds__(256) k_normalize(const float* __restrict__ S,
                                                    const double* __restrict__ W,
+                                                   const double* __restrict__ Wn,
                                                    const int32_t* __restrict__ target_slot,
                                                    int64_t nslots, int64_t nchan, int64_t ntarget,
                                                    float* __restrict__ cube, float* __restrict__ wout) {
@@ -422,18 +425,20 @@ __global__ void __launch_bounds__(256) k_normalize(const float* __restrict__ S,
   if (t >= ntarget) return;
   const int64_t c = blockIdx.y;
   const int64_t s = target_slot[t];
-  const double w = W[s];
-  if (cube) cube[c * ntarget + t] = w > 0.0 ? (float)((double)S[c * nslots + s] / w) : qnan_f();
-  if (wout && c == 0) wout[t] = (float)w;
+  if (cube) {
+    const double wn = Wn[s];
+    cube[c * ntarget + t] = wn > 0.0 ? (float)((double)S[c * nslots + s] / wn) : qnan_f();
+  }
+  if (wout && c == 0) wout[t] = (float)W[s];
 }
 
-hipError_t launch_normalize(const float* S, const double* W, const int32_t* target_slot,
-                            int64_t nslots, int64_t nchan, int64_t ntarget, float* cube,
-                            float* wout, hipStream_t st) {
+hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
+                            const int32_t* target_slot, int64_t nslots, int64_t nchan,
+                            int64_t ntarget, float* cube, float* wout, hipStream_t st) {
   if (ntarget <= 0) return hipSuccess;
   const int64_t gy = cube ? nchan : 1;
   hipLaunchKernelGGL(k_normalize, dim3((unsigned)((ntarget + 255) / 256), (unsigned)gy), dim3(256),
-                     0, st, S, W, target_slot, nslots, nchan, ntarget, cube, wout);
+                     0, st, S, W, Wn, target_slot, nslots, nchan, ntarget, cube, wout);
   return hipGetLastError();
 }
 

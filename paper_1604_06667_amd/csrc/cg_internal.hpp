@@ -84,7 +84,7 @@ hipError_t launch_prep(const double* lon, const double* lat, int64_t n, int64_t 
                        uint32_t* keys, uint32_t* vals, int* flag, hipStream_t st);
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                       uint32_t* hist, int64_t n, int bits, bool* result_in_tmp, hipStream_t st);
-size_t radix_hist_elems(int64_t n);
+size_t radix_hist_elems(int64_t n);   // includes 256 digit totals
 hipError_t launch_ring_offsets(const uint32_t* keys, int64_t n, int64_t nside, uint32_t* ring_off,
                                hipStream_t st);
 hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int64_t n,
@@ -116,7 +116,8 @@ hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, cons
 enum AccMode { ACC_OVERWRITE = 0, ACC_ADD = 1, ACC_FINAL = 2 };
 struct OutView {
   float* S;            // [nchan][nslots] accumulator (ACC_OVERWRITE / ACC_ADD)
-  double* W;           // [nslots]
+  double* W;           // [nslots] weight map (Eq. 2)
+  double* Wn;          // [nslots] normaliser: sum of the weights as they entered the products
   float* cube;         // ACC_FINAL: normalised output in user layout
   float* wout;         // ACC_FINAL: weights in user layout (may be null)
   const int32_t* slot_target;
@@ -133,9 +134,9 @@ bool mfma_available();
 hipError_t launch_stats(const TileView& tv, const KernelParams& kp, int64_t ntiles,
                         const uint32_t* vals, const int32_t* slot_target, int32_t* counts,
                         uint64_t* hashes, hipStream_t st);
-hipError_t launch_normalize(const float* S, const double* W, const int32_t* target_slot,
-                            int64_t nslots, int64_t nchan, int64_t ntarget, float* cube,
-                            float* wout, hipStream_t st);
+hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
+                            const int32_t* target_slot, int64_t nslots, int64_t nchan,
+                            int64_t ntarget, float* cube, float* wout, hipStream_t st);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
 
 }  // namespace cg

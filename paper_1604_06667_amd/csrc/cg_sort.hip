@@ -68,42 +68,57 @@ __global__ void __launch_bounds__(kSortThreads) k_hist(const uint32_t* __restric
   hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
 }
 
-// Single-workgroup exclusive scan (in place) of a uint32 array.
-__global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ a, int64_t n) {
-  __shared__ uint32_t part[1024];
+// Exclusive scan of each digit's per-block counts (one workgroup per digit,
+// coalesced), leaving the digit totals in totals[256].
+__global__ void __launch_bounds__(256) k_digit_scan(uint32_t* __restrict__ hist, int64_t nblocks,
+                                                    uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s[256];
   const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = (int64_t)t * per;
-  const int64_t e = b + per < n ? b + per : n;
-  uint32_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += a[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = (t >= off) ? part[t - off] : 0u;
+  uint32_t* h = hist + (int64_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
+    const int64_t i = b0 + t;
+    const uint32_t v = i < nblocks ? h[i] : 0u;
+    s[t] = v;
     __syncthreads();
-    part[t] += v;
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t u = t >= off ? s[t - off] : 0u;
+      __syncthreads();
+      s[t] += u;
+      __syncthreads();
+    }
+    if (i < nblocks) h[i] = carry + s[t] - v;
+    carry += s[255];
     __syncthreads();
   }
-  uint32_t run = part[t] - s;
-  for (int64_t i = b; i < e; ++i) {
-    const uint32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
+  if (t == 0) totals[blockIdx.x] = carry;
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
-    const uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int64_t nblocks,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   constexpr int NW = kSortThreads / 64;
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[NW][256];
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
-  base[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+  // digit bases: exclusive scan of the 256 digit totals
+  {
+    const uint32_t v = totals[t];
+    base[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t u = t >= off ? base[t - off] : 0u;
+      __syncthreads();
+      base[t] += u;
+      __syncthreads();
+    }
+    const uint32_t excl = base[t] - v;
+    __syncthreads();
+    base[t] = excl + hist[(int64_t)t * nblocks + blockIdx.x];
+  }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t blk = (int64_t)blockIdx.x * kSortTile;
   for (int r = 0; r < kSortItems; ++r) {
@@ -148,7 +163,7 @@ __global__ void __launch_bounds__(kSortThreads) k_scatter(
 
 size_t radix_hist_elems(int64_t n) {
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
-  return (size_t)(nb < 1 ? 1 : nb) * 256;
+  return (size_t)(nb < 1 ? 1 : nb) * 256 + 256;
 }
 
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
@@ -161,9 +176,10 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, n, shift, hist,
                        nb);
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, hist, nb * 256);
+    uint32_t* totals = hist + nb * 256;
+    hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, hist, nb, totals);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, vi, n, shift,
-                       hist, nb, ko, vo);
+                       hist, totals, nb, ko, vo);
     uint32_t* tk = ki; ki = ko; ko = tk;
     uint32_t* tv = vi; vi = vo; vo = tv;
     in_tmp = !in_tmp;
