@@ -95,12 +95,14 @@ struct cg_gridder {
   DevBuf S, W, Wn;
   bool fresh = true;
   DevBuf flag;
+  DevBuf zrow;   // nchan zeros of the widest data type
   DevBuf keys, vals, keys2, vals2, hist, ring_off, sx, sdata, ranges, nranges, ncand, cand_off,
-      cand;
+      cand, crow, cxyz;
   const uint32_t* sorted_keys = nullptr;
   const uint32_t* sorted_vals = nullptr;
   int64_t last_n = 0;
   int64_t last_ncand = 0;
+  int64_t ncap = 1;
   uint64_t* h_word = nullptr;  // pinned host word
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -125,6 +127,8 @@ cg_status alloc_targets(cg_gridder* g) {
   CG_HIP(ensure(g->Wn, sizeof(double) * g->nslots), "alloc weights");
   CG_HIP(ensure(g->flag, sizeof(int)), "alloc flag");
   CG_HIP(hipMemset(g->flag.p, 0, sizeof(int)), "clear flag");
+  CG_HIP(ensure(g->zrow, sizeof(double) * g->nchan), "alloc zero row");
+  CG_HIP(hipMemset(g->zrow.p, 0, sizeof(double) * g->nchan), "clear zero row");
   CG_HIP(hipHostMalloc((void**)&g->h_word, sizeof(uint64_t) * 2, hipHostMallocDefault),
          "pinned word");
   return CG_OK;
@@ -203,10 +207,15 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
   const int64_t total = (int64_t)g->h_word[0];
   g->last_ncand = total;
   g->last_n = n;
-  CG_HIP(ensure(g->cand, sizeof(uint32_t) * (total > 0 ? total : 1)), "alloc candidates");
+  const int64_t tc = total > 0 ? total : 1;
+  CG_HIP(ensure(g->cand, sizeof(uint32_t) * tc), "alloc candidates");
+  CG_HIP(ensure(g->crow, sizeof(uint32_t) * tc), "alloc candidates");
+  CG_HIP(ensure(g->cxyz, sizeof(double) * 3 * tc), "alloc candidates");
+  g->ncap = tc;
   CG_HIP(cg::launch_expand(g->range_off.as<uint64_t>(), g->ranges.as<uint32_t>(),
                            g->nranges.as<uint32_t>(), g->cand_off.as<uint64_t>(), g->ntiles,
-                           g->cand.as<uint32_t>(), st),
+                           g->sorted_vals, g->sx.as<double>(), n, g->cand.as<uint32_t>(),
+                           g->crow.as<uint32_t>(), g->cxyz.as<double>(), g->ncap, st),
          "expand");
   return CG_OK;
 }
@@ -217,9 +226,11 @@ cg::TileView tile_view(const cg_gridder* g) {
   tv.tll = g->tll.as<double>();
   tv.cand_off = g->cand_off.as<uint64_t>();
   tv.cand = g->cand.as<uint32_t>();
-  tv.sx = g->sx.as<double>();
+  tv.crow = g->crow.as<uint32_t>();
+  tv.cxyz = g->cxyz.as<double>();
   tv.nslots = g->nslots;
-  tv.nsorted = g->last_n;
+  tv.ncap = g->ncap;
+  tv.ntiles = g->ntiles;
   return tv;
 }
 
@@ -254,12 +265,11 @@ cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
     CG_HIP(hipEventRecord(pe->first, st), "event record");
   }
   if (g->prec == CG_PREC_FP32) {
-    CG_HIP(cg::launch_gather_fp32(tv, g->kp, g->ntiles, g->sorted_vals, data, dtype, ld,
-                                  g->sdata.as<float>(), g->nchan, ov, st),
+    CG_HIP(cg::launch_gather_fp32(tv, g->kp, data, dtype, ld, g->sdata.as<float>(), g->nchan, ov,
+                                  st),
            "gather");
   } else {
-    CG_HIP(cg::launch_gather_mfma(tv, g->kp, g->ntiles, g->sorted_vals, data, dtype, ld, g->nchan,
-                                  g->prec, ov, st),
+    CG_HIP(cg::launch_gather_mfma(tv, g->kp, data, g->zrow.p, dtype, ld, g->nchan, g->prec, ov, st),
            "gather (mfma)");
   }
   if (pe) CG_HIP(hipEventRecord(pe->second, st), "event record");
@@ -565,8 +575,7 @@ cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double*
   if (!lon_deg || !lat_deg) return fail(CG_E_INVALID, "null coordinate pointer");
   s = run_lookup(g, lon_deg, lat_deg, nsamples, nullptr, CG_F32, g->nchan, false, st);
   if (s != CG_OK) return s;
-  CG_HIP(cg::launch_stats(tile_view(g), g->kp, g->ntiles, g->sorted_vals,
-                          g->slot_target.as<int32_t>(), counts, hashes, st),
+  CG_HIP(cg::launch_stats(tile_view(g), g->kp, g->slot_target.as<int32_t>(), counts, hashes, st),
          "stats");
   return CG_OK;
 }
@@ -617,9 +626,10 @@ void cg_destroy(cg_gridder* g) {
     (void)hipEventDestroy(e.second);
   }
   DevBuf* bufs[] = {&g->txyz, &g->tll, &g->slot_target, &g->target_slot, &g->caps,
-                    &g->ring_first, &g->span_bound, &g->range_off, &g->S, &g->W, &g->Wn, &g->flag,
+                    &g->ring_first, &g->span_bound, &g->range_off, &g->S, &g->W, &g->Wn, &g->flag, &g->zrow,
                     &g->keys, &g->vals, &g->keys2, &g->vals2, &g->hist, &g->ring_off, &g->sx,
-                    &g->sdata, &g->ranges, &g->nranges, &g->ncand, &g->cand_off, &g->cand};
+                    &g->sdata, &g->ranges, &g->nranges, &g->ncand, &g->cand_off, &g->cand,
+                    &g->crow, &g->cxyz};
   for (DevBuf* b : bufs) b->release();
   if (g->h_word) (void)hipHostFree(g->h_word);
   delete g;

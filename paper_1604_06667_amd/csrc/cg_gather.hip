@@ -46,7 +46,7 @@ template <int CMAX>
 __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
                                                   const float* __restrict__ sdata, int64_t nchan,
                                                   OutView ov) {
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = tile_of_block(blockIdx.x, tv.ntiles);
   const int lane = threadIdx.x;
   const int64_t slot = tile * kTile + lane;
   __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
@@ -60,14 +60,14 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
   double wacc = 0.0;
   const uint64_t c0 = tv.cand_off[tile], c1 = tv.cand_off[tile + 1];
-  const int64_t cap = tv.nsorted;
+  const int64_t cap = tv.ncap;
   for (uint64_t base = c0; base < c1; base += kChunk) {
     const int kmax = (int)((c1 - base) < (uint64_t)kChunk ? (c1 - base) : (uint64_t)kChunk);
     if (lane < kmax) {
       const int64_t pos = tv.cand[base + lane];
-      s_x[lane] = tv.sx[pos];
-      s_y[lane] = tv.sx[cap + pos];
-      s_z[lane] = tv.sx[2 * cap + pos];
+      s_x[lane] = tv.cxyz[base + lane];
+      s_y[lane] = tv.cxyz[cap + base + lane];
+      s_z[lane] = tv.cxyz[2 * cap + base + lane];
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
         if (c < nchan) s_d[lane * CMAX + c] = sdata[pos * nchan + c];
@@ -154,7 +154,6 @@ __device__ __forceinline__ void load_row_vec(const T* __restrict__ p, int nvalid
 
 template <int VEC, int KT, typename T>
 __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
-                                                   const uint32_t* __restrict__ vals,
                                                    const T* __restrict__ data, int64_t ld,
                                                    int64_t nchan, int vec_ok_in, OutView ov) {
   constexpr int CB = 64 * VEC;
@@ -165,11 +164,12 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
   __shared__ __attribute__((aligned(16))) float s_d[kChunk * CB];
   __shared__ double s_t[kTile][9];   // target xyz, major axis, minor axis
   __shared__ double s_w[kTile];
-  const int64_t tile = blockIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.y * CB;
+  int64_t tile, pass;
+  work_of_block(blockIdx.x, tv.ntiles, (nchan + CB - 1) / CB, &tile, &pass);
+  const int64_t c0 = pass * CB;
   const int t = threadIdx.x, lane = t & 63, wv_id = t >> 6;
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.nsorted;
+  const int64_t cap = tv.ncap;
   if (t < kTile) {
     const int64_t slot = tile * kTile + t;
     const double x = tv.txyz[slot];
@@ -196,11 +196,10 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
   for (uint64_t base = cb0; base < cb1; base += kChunk) {
     const int kmax = (int)((cb1 - base) < (uint64_t)kChunk ? (cb1 - base) : (uint64_t)kChunk);
     if (t < kmax) {
-      const int64_t pos = tv.cand[base + t];
-      s_x[t] = tv.sx[pos];
-      s_y[t] = tv.sx[cap + pos];
-      s_z[t] = tv.sx[2 * cap + pos];
-      s_row[t] = (int64_t)vals[pos] * ld;
+      s_x[t] = tv.cxyz[base + t];
+      s_y[t] = tv.cxyz[cap + base + t];
+      s_z[t] = tv.cxyz[2 * cap + base + t];
+      s_row[t] = (int64_t)tv.crow[base + t] * ld;
     }
     __syncthreads();
     for (int r = wv_id; r < kmax; r += NWV) {
@@ -288,7 +287,7 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
       ov.S[(c0 + c) * ns + slot] = o;
     }
   }
-  if (blockIdx.y == 0 && t < kTile) {
+  if (pass == 0 && t < kTile) {
     const int64_t slot = tile * kTile + t;
     if (fin) {
       const int32_t tg = ov.slot_target[slot];
@@ -301,51 +300,48 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
 }
 
 template <int VEC, typename T>
-static void launch_cl(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                      const uint32_t* vals, const void* data, int64_t ld, int64_t nchan,
-                      const OutView& ov, hipStream_t st) {
+static void launch_cl(const TileView& tv, const KernelParams& kp, const void* data, int64_t ld,
+                      int64_t nchan, const OutView& ov, hipStream_t st) {
   const int64_t ncb = (nchan + 64 * VEC - 1) / (64 * VEC);
-  const dim3 g((unsigned)ntiles, (unsigned)ncb), b(512);
+  const dim3 g((unsigned)(tv.ntiles * ncb)), b(512);
   // vector loads need every row start aligned to VEC elements
   const int vec_ok = (ld % VEC == 0) && ((uintptr_t)data % (VEC * sizeof(T)) == 0) ? 1 : 0;
   if (kp.type == 0)
-    hipLaunchKernelGGL((k_gather_cl<VEC, 0, T>), g, b, 0, st, tv, kp, vals, (const T*)data, ld,
-                       nchan, vec_ok, ov);
+    hipLaunchKernelGGL((k_gather_cl<VEC, 0, T>), g, b, 0, st, tv, kp, (const T*)data, ld, nchan,
+                       vec_ok, ov);
   else
-    hipLaunchKernelGGL((k_gather_cl<VEC, 1, T>), g, b, 0, st, tv, kp, vals, (const T*)data, ld,
-                       nchan, vec_ok, ov);
+    hipLaunchKernelGGL((k_gather_cl<VEC, 1, T>), g, b, 0, st, tv, kp, (const T*)data, ld, nchan,
+                       vec_ok, ov);
 }
 
 template <int VEC>
-static void launch_cl_dt(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                         const uint32_t* vals, const void* data, int dtype, int64_t ld,
-                         int64_t nchan, const OutView& ov, hipStream_t st) {
+static void launch_cl_dt(const TileView& tv, const KernelParams& kp, const void* data, int dtype,
+                         int64_t ld, int64_t nchan, const OutView& ov, hipStream_t st) {
   switch (dtype) {
-    case 0: launch_cl<VEC, double>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
-    case 1: launch_cl<VEC, float>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
-    case 2: launch_cl<VEC, _Float16>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
-    default: launch_cl<VEC, uint16_t>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
+    case 0: launch_cl<VEC, double>(tv, kp, data, ld, nchan, ov, st); break;
+    case 1: launch_cl<VEC, float>(tv, kp, data, ld, nchan, ov, st); break;
+    case 2: launch_cl<VEC, _Float16>(tv, kp, data, ld, nchan, ov, st); break;
+    default: launch_cl<VEC, uint16_t>(tv, kp, data, ld, nchan, ov, st); break;
   }
 }
 
-hipError_t launch_gather_fp32(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                              const uint32_t* vals, const void* data, int dtype, int64_t ld,
-                              const float* sdata, int64_t nchan, const OutView& ov,
-                              hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_gather_fp32(const TileView& tv, const KernelParams& kp, const void* data,
+                              int dtype, int64_t ld, const float* sdata, int64_t nchan,
+                              const OutView& ov, hipStream_t st) {
+  if (tv.ntiles <= 0) return hipSuccess;
   if (nchan <= kSmallC) {
-    const dim3 g((unsigned)ntiles), b(64);
+    const dim3 g((unsigned)tv.ntiles), b(64);
     if (nchan <= 1) hipLaunchKernelGGL(k_gather_tl<1>, g, b, 0, st, tv, kp, sdata, nchan, ov);
     else if (nchan <= 2) hipLaunchKernelGGL(k_gather_tl<2>, g, b, 0, st, tv, kp, sdata, nchan, ov);
     else if (nchan <= 4) hipLaunchKernelGGL(k_gather_tl<4>, g, b, 0, st, tv, kp, sdata, nchan, ov);
     else if (nchan <= 8) hipLaunchKernelGGL(k_gather_tl<8>, g, b, 0, st, tv, kp, sdata, nchan, ov);
     else hipLaunchKernelGGL(k_gather_tl<16>, g, b, 0, st, tv, kp, sdata, nchan, ov);
   } else if (nchan <= 64) {
-    launch_cl_dt<1>(tv, kp, ntiles, vals, data, dtype, ld, nchan, ov, st);
+    launch_cl_dt<1>(tv, kp, data, dtype, ld, nchan, ov, st);
   } else if (nchan <= 128) {
-    launch_cl_dt<2>(tv, kp, ntiles, vals, data, dtype, ld, nchan, ov, st);
+    launch_cl_dt<2>(tv, kp, data, dtype, ld, nchan, ov, st);
   } else {
-    launch_cl_dt<4>(tv, kp, ntiles, vals, data, dtype, ld, nchan, ov, st);
+    launch_cl_dt<4>(tv, kp, data, dtype, ld, nchan, ov, st);
   }
   return hipGetLastError();
 }
@@ -362,17 +358,16 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
 }
 
 __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
-                                              const uint32_t* __restrict__ vals,
                                               const int32_t* __restrict__ slot_target,
                                               int32_t* __restrict__ counts,
                                               uint64_t* __restrict__ hashes) {
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = tile_of_block(blockIdx.x, tv.ntiles);
   const int lane = threadIdx.x;
   const int64_t slot = tile * kTile + lane;
   __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
   __shared__ uint32_t s_n[kChunk];
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.nsorted;
+  const int64_t cap = tv.ncap;
   const double tx = tv.txyz[slot], ty = tv.txyz[ns + slot], tz = tv.txyz[2 * ns + slot];
   int32_t cnt = 0;
   uint64_t h = 0;
@@ -380,11 +375,10 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
   for (uint64_t base = c0; base < c1; base += kChunk) {
     const int kmax = (int)((c1 - base) < (uint64_t)kChunk ? (c1 - base) : (uint64_t)kChunk);
     if (lane < kmax) {
-      const int64_t pos = tv.cand[base + lane];
-      s_x[lane] = tv.sx[pos];
-      s_y[lane] = tv.sx[cap + pos];
-      s_z[lane] = tv.sx[2 * cap + pos];
-      s_n[lane] = vals[pos];
+      s_x[lane] = tv.cxyz[base + lane];
+      s_y[lane] = tv.cxyz[cap + base + lane];
+      s_z[lane] = tv.cxyz[2 * cap + base + lane];
+      s_n[lane] = tv.crow[base + lane];
     }
     __syncthreads();
     for (int k = 0; k < kmax; ++k) {
@@ -403,11 +397,10 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
   }
 }
 
-hipError_t launch_stats(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                        const uint32_t* vals, const int32_t* slot_target, int32_t* counts,
-                        uint64_t* hashes, hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stats, dim3((unsigned)ntiles), dim3(64), 0, st, tv, kp, vals, slot_target,
+hipError_t launch_stats(const TileView& tv, const KernelParams& kp, const int32_t* slot_target,
+                        int32_t* counts, uint64_t* hashes, hipStream_t st) {
+  if (tv.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stats, dim3((unsigned)tv.ntiles), dim3(64), 0, st, tv, kp, slot_target,
                      counts, hashes);
   return hipGetLastError();
 }

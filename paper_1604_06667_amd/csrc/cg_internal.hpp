@@ -30,11 +30,34 @@ struct TileView {
   const double* txyz;          // [3][nslots] target unit vectors (NaN: no target)
   const double* tll;           // [2][nslots] target lon, lat in radians (gauss2d axes)
   const uint64_t* cand_off;    // [ntiles + 1] candidate offsets
-  const uint32_t* cand;        // sorted-sample positions
-  const double* sx;            // [3][nvalid] sorted sample unit vectors
+  const uint32_t* cand;        // [ncand] sorted-sample position of each candidate
+  const uint32_t* crow;        // [ncand] input index (data row) of each candidate
+  const double* cxyz;          // [3][ncap] unit vector of each candidate
   int64_t nslots;
-  int64_t nsorted;
+  int64_t ncap;                // stride of cxyz
+  int64_t ntiles;
 };
+
+// Block -> tile map that keeps consecutive tiles on one XCD: workgroups are
+// dispatched to the 8 XCDs round robin, so block b runs on XCD b % 8; XCD k
+// is given the k-th contiguous run of tiles, walked in order, so that tiles
+// sharing candidate samples are resident together in that XCD's L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t ntiles) {
+  const int64_t k = b % kNumXcd;
+  const int64_t j = b / kNumXcd;
+  int64_t start = 0;
+  for (int64_t q = 0; q < k; ++q) start += (ntiles - q + kNumXcd - 1) / kNumXcd;
+  return start + j;
+}
+// Same for a 1-D grid of ntiles * npass work items (channel passes of a
+// tile are adjacent, so they run on the same XCD).
+__device__ __forceinline__ void work_of_block(int64_t b, int64_t ntiles, int64_t npass,
+                                              int64_t* tile, int64_t* pass) {
+  const int64_t v = tile_of_block(b, ntiles * npass);
+  *tile = v / npass;
+  *pass = v % npass;
+}
 
 // ---------------------------------------------------------------- device math
 
@@ -110,7 +133,9 @@ hipError_t launch_tile_ranges(const double* caps, int64_t ntiles, int64_t nside,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st);
 hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
-                         const uint64_t* cand_off, int64_t ntiles, uint32_t* cand, hipStream_t st);
+                         const uint64_t* cand_off, int64_t ntiles, const uint32_t* vals,
+                         const double* sx, int64_t nsorted, uint32_t* cand, uint32_t* crow,
+                         double* cxyz, int64_t ncap, hipStream_t st);
 
 // contraction kernels
 enum AccMode { ACC_OVERWRITE = 0, ACC_ADD = 1, ACC_FINAL = 2 };
@@ -124,16 +149,16 @@ struct OutView {
   int64_t ntarget;
   int mode;
 };
-hipError_t launch_gather_fp32(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                              const uint32_t* vals, const void* data, int dtype, int64_t ld,
-                              const float* sdata, int64_t nchan, const OutView& ov, hipStream_t st);
-hipError_t launch_gather_mfma(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                              const uint32_t* vals, const void* data, int dtype, int64_t ld,
-                              int64_t nchan, int prec, const OutView& ov, hipStream_t st);
+hipError_t launch_gather_fp32(const TileView& tv, const KernelParams& kp, const void* data,
+                              int dtype, int64_t ld, const float* sdata, int64_t nchan,
+                              const OutView& ov, hipStream_t st);
+// zrow: device row of at least nchan zeros of the data type (8 * nchan bytes)
+hipError_t launch_gather_mfma(const TileView& tv, const KernelParams& kp, const void* data,
+                              const void* zrow, int dtype, int64_t ld, int64_t nchan, int prec,
+                              const OutView& ov, hipStream_t st);
 bool mfma_available();
-hipError_t launch_stats(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                        const uint32_t* vals, const int32_t* slot_target, int32_t* counts,
-                        uint64_t* hashes, hipStream_t st);
+hipError_t launch_stats(const TileView& tv, const KernelParams& kp, const int32_t* slot_target,
+                        int32_t* counts, uint64_t* hashes, hipStream_t st);
 hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
                             const int32_t* target_slot, int64_t nslots, int64_t nchan,
                             int64_t ntarget, float* cube, float* wout, hipStream_t st);

@@ -23,6 +23,8 @@
 namespace cg {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
@@ -43,6 +45,30 @@ template <bool F16>
 __device__ __forceinline__ float from_bits(uint16_t b) {
   if constexpr (F16) return (float)__builtin_bit_cast(_Float16, b);
   else return __uint_as_float((uint32_t)b << 16);
+}
+
+// Two floats -> two packed 16-bit values (round to nearest even), element a
+// in the low half.
+template <bool F16>
+__device__ __forceinline__ uint32_t cvt_pk(float a, float b) {
+  if constexpr (F16) {
+    return (uint32_t)to_bits<true>(a) | ((uint32_t)to_bits<true>(b) << 16);
+  } else {
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+  }
+}
+
+// The two packed values as floats.
+template <bool F16>
+__device__ __forceinline__ float unpk_lo(uint32_t p) {
+  if constexpr (F16) return from_bits<true>((uint16_t)(p & 0xffffu));
+  else return __uint_as_float(p << 16);
+}
+template <bool F16>
+__device__ __forceinline__ float unpk_hi(uint32_t p) {
+  if constexpr (F16) return from_bits<true>((uint16_t)(p >> 16));
+  else return __uint_as_float(p & 0xffff0000u);
 }
 
 template <typename T>
@@ -80,55 +106,86 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, int nvalid, bool 
 }
 
 // MODE 0: BF16 with hi/lo split of data and weights, three products per
-//         block (hi*hi + lo*hi + hi*lo), 16 samples per chunk;
-// MODE 1: FP16, one product per block, 32 samples per chunk.
-template <int NW, int BPW, int KT, int MODE, typename T>
+//         block (hi*hi + lo*hi + hi*lo);
+// MODE 1: FP16, one product per block.
+//
+// Work of one workgroup: one tile (64 targets) x CP channels.  Wavefront w
+// owns channel blocks [w*BPW, (w+1)*BPW) of 32 channels; lane l holds
+// channel l%32 of a block and the 8 samples 8*(l/32) .. +7 of a 16-sample
+// chunk, i.e. exactly its MFMA A operand, so the data never passes through
+// LDS: each lane loads its 8 values straight from the sample rows (one
+// 128-byte segment per row and half-wave) and converts them in registers.
+// Only the 64 x 16 weight block is shared through LDS (double buffered).
+// Software pipeline, one barrier per chunk: while chunk i is on the matrix
+// cores, the same wavefront computes the weight block of chunk i+1 and
+// reloads its data registers with chunk i+1; candidate records run two
+// chunks ahead through a three-deep LDS ring.  Past-the-end candidates point
+// at a row of zeros, so the loads need no bounds selects.  FULL: the channel
+// count is a multiple of CP (no channel bounds checks).
+template <int NW, int BPW, int KT, int MODE, bool FULL, typename T>
 __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelParams kp,
-                                                         const uint32_t* __restrict__ vals,
-                                                         const T* __restrict__ data, int64_t ld,
-                                                         int64_t nchan, int vec_ok_in,
-                                                         OutView ov) {
+                                                         const T* __restrict__ data,
+                                                         const T* __restrict__ zrow, int64_t ld,
+                                                         int64_t nchan, OutView ov) {
   constexpr bool F16 = MODE == 1;
   constexpr bool SPLIT = MODE == 0;
-  constexpr int NS = SPLIT ? 2 : 1;              // hi (+ lo) planes
-  constexpr int MK = SPLIT ? 16 : 32;            // candidate samples per chunk
-  constexpr int KP = MK + 8;                     // padded LDS row, multiple of 8 elements
-  constexpr int NT = NW * 64;
-  constexpr int CP = NW * BPW * 32;              // channels per pass (grid.y)
-  constexpr int NITEMS = (MK / 4) * (CP / 4);    // 4 samples x 4 channels per item
+  constexpr bool BF16IN = std::is_same<T, uint16_t>::value;
+  constexpr int NS = SPLIT ? 2 : 1;              // hi (+ lo) parts
+  constexpr int MK = 16;                         // candidate samples per chunk
+  constexpr int KP = MK + 8;                     // padded LDS row of the weight block
+  constexpr int CP = NW * BPW * 32;              // channels per pass
   using opv_t = typename std::conditional<F16, f16x8_t, bf16x8_t>::type;
-  __shared__ __attribute__((aligned(16))) uint16_t s_dt[NS][CP * KP];    // data^T  [channel][sample]
-  __shared__ __attribute__((aligned(16))) uint16_t s_wt[NS][kTile * KP]; // weights [target][sample]
-  __shared__ double s_c[MK][3];
-  __shared__ int64_t s_row[MK];
+  __shared__ __attribute__((aligned(16))) uint16_t s_wt[2][NS][kTile * KP];  // [buf][part][target][sample]
+  __shared__ double s_c[3][MK][3];
+  __shared__ const T* s_row[3][MK];
   __shared__ double s_red[2][NW][kTile];
   __shared__ double s_wfin[2][kTile];
+  __shared__ double s_tg[kTile][KT == 1 ? 9 : 3];   // target xyz (+ major, minor axis)
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t tile = blockIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.y * CP;
+  int64_t tile, pass;
+  work_of_block(blockIdx.x, tv.ntiles, (nchan + CP - 1) / CP, &tile, &pass);
+  const int64_t c0 = pass * CP;
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.nsorted;
-  const bool vec_ok = vec_ok_in != 0;
+  const int64_t cap = tv.ncap;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  const int cl = lane & 31;      // channel within a 32-channel block / target within a 32-target block
+  const int kh = lane >> 5;      // which 8 samples of the chunk this lane holds
+  const int64_t cbase = c0 + wv * BPW * 32 + cl;   // this lane's channel in block 0
+  bool bvalid[BPW];
+#pragma unroll
+  for (int b = 0; b < BPW; ++b) bvalid[b] = FULL || (cbase + 32 * b < nchan);
 
-  // this thread's target for the weight block
+  if (t < kTile) {
+    const int64_t wslot = tile * kTile + t;
+    const double x = tv.txyz[wslot];
+    s_tg[t][0] = x;
+    s_tg[t][1] = tv.txyz[ns + wslot];
+    s_tg[t][2] = tv.txyz[2 * ns + wslot];
+    if constexpr (KT == 1) {
+      double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+      if (isfinite(x)) {
+        double sa, ca, sd, cd;
+        sincos(tv.tll[wslot], &sa, &ca);
+        sincos(tv.tll[ns + wslot], &sd, &cd);
+        const double ex = -sa, ey = ca, nx = -sd * ca, ny = -sd * sa, nz = cd;
+        a[0] = kp.cospa * nx + kp.sinpa * ex;
+        a[1] = kp.cospa * ny + kp.sinpa * ey;
+        a[2] = kp.cospa * nz;
+        b[0] = kp.cospa * ex - kp.sinpa * nx;
+        b[1] = kp.cospa * ey - kp.sinpa * ny;
+        b[2] = -kp.sinpa * nz;
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        s_tg[t][3 + q] = a[q];
+        s_tg[t][6 + q] = b[q];
+      }
+    }
+  }
+  // this thread's target in the weight block and its candidates kg, kg + NW, ...
   const int nw = t & 63;
   const int kg = t >> 6;
-  const int64_t wslot = tile * kTile + nw;
-  const double tx = tv.txyz[wslot], ty = tv.txyz[ns + wslot], tz = tv.txyz[2 * ns + wslot];
-  double ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
-  if (KT == 1 && isfinite(tx)) {
-    double sa, ca, sd, cd;
-    sincos(tv.tll[wslot], &sa, &ca);
-    sincos(tv.tll[ns + wslot], &sd, &cd);
-    const double ex = -sa, ey = ca, nx = -sd * ca, ny = -sd * sa, nz = cd;
-    ax = kp.cospa * nx + kp.sinpa * ex;
-    ay = kp.cospa * ny + kp.sinpa * ey;
-    az = kp.cospa * nz;
-    bx = kp.cospa * ex - kp.sinpa * nx;
-    by = kp.cospa * ey - kp.sinpa * ny;
-    bz = -kp.sinpa * nz;
-  }
   double wsum = 0.0, wsum_r = 0.0;
 
   f32x16_t acc[BPW][2];
@@ -140,114 +197,145 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
       for (int j = 0; j < 16; ++j) acc[b][nb][j] = 0.0f;
 
   const uint64_t cb0 = tv.cand_off[tile], cb1 = tv.cand_off[tile + 1];
-  const double nan = __longlong_as_double(0x7ff8000000000000ll);
-  for (uint64_t base = cb0; base < cb1; base += MK) {
-    const int kmax = (int)((cb1 - base) < (uint64_t)MK ? (cb1 - base) : (uint64_t)MK);
+  const int64_t nchunks = (int64_t)((cb1 - cb0 + MK - 1) / MK);
+
+  // candidate record of chunk ch for thread t < MK (NaN / zero row past the end)
+  double rx = nan, ry = nan, rz = nan;
+  const T* rrow = zrow;
+  auto load_rec = [&](int64_t ch) {
+    const uint64_t q = cb0 + (uint64_t)ch * MK + t;
+    if (ch < nchunks && q < cb1) {
+      rx = tv.cxyz[q];
+      ry = tv.cxyz[cap + q];
+      rz = tv.cxyz[2 * cap + q];
+      rrow = data + (int64_t)tv.crow[q] * ld;
+    } else {
+      rx = ry = rz = nan;
+      rrow = zrow - c0;   // + channel offsets below stays inside the zero row
+    }
+  };
+  auto put_rec = [&](int buf) {
+    s_c[buf][t][0] = rx;
+    s_c[buf][t][1] = ry;
+    s_c[buf][t][2] = rz;
+    s_row[buf][t] = rrow;
+  };
+  // weight of candidate k of the chunk in record buffer rb -> weight buffer wb
+  auto weight = [&](int rb, int wb, int k) {
+    const double dx = s_c[rb][k][0] - s_tg[nw][0];
+    const double dy = s_c[rb][k][1] - s_tg[nw][1];
+    const double dz = s_c[rb][k][2] - s_tg[nw][2];
+    const double c2 = dx * dx + dy * dy + dz * dz;
+    float w = 0.0f;
+    if (c2 <= kp.cs2) {
+      if constexpr (KT == 0)
+        w = exp2_neg(chord2_to_d2(c2) * kp.k1);
+      else
+        w = pair_weight(kp, c2, dx, dy, dz, s_tg[nw][3], s_tg[nw][4], s_tg[nw][5], s_tg[nw][6],
+                        s_tg[nw][7], s_tg[nw][8]);
+    }
+    const uint16_t whi = to_bits<F16>(w);
+    float wr = from_bits<F16>(whi);
+    s_wt[wb][0][nw * KP + k] = whi;
+    if constexpr (SPLIT) {
+      const uint16_t wlo = to_bits<F16>(w - wr);
+      s_wt[wb][NS - 1][nw * KP + k] = wlo;
+      wr += from_bits<F16>(wlo);
+    }
+    wsum += (double)w;
+    wsum_r += (double)wr;
+  };
+  // this lane's A-operand values (raw input) of one chunk
+  float raw[BPW][8];
+  auto load_block = [&](int rb, int b) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const T* p = s_row[rb][8 * kh + i] + cbase + 32 * b;
+      raw[b][i] = bvalid[b] ? in_f32<T>(p) : 0.0f;
+    }
+  };
+
+  // prologue: records of chunks 0, 1 in LDS, of chunk 2 in registers; the
+  // weights and data of chunk 0
+  if (t < MK) {
+    load_rec(0);
+    put_rec(0);
+    load_rec(1);
+    put_rec(1);
+    load_rec(2);
+  }
+  __syncthreads();
+  if (nchunks > 0) {
+#pragma unroll
+    for (int k = kg; k < MK; k += NW) weight(0, 0, k);
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) load_block(0, b);
+  }
+
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int wc = (int)(ch & 1);                 // weight buffer of chunk ch
+    const int r1 = (int)((ch + 1) % 3);           // record buffer of chunk ch+1
+    __syncthreads();
+    // records: publish chunk ch+2, fetch chunk ch+3
     if (t < MK) {
-      if (t < kmax) {
-        const int64_t pos = tv.cand[base + t];
-        s_c[t][0] = tv.sx[pos];
-        s_c[t][1] = tv.sx[cap + pos];
-        s_c[t][2] = tv.sx[2 * cap + pos];
-        s_row[t] = (int64_t)vals[pos] * ld;
-      } else {
-        s_c[t][0] = nan;
-        s_c[t][1] = nan;
-        s_c[t][2] = nan;
-        s_row[t] = -1;
-      }
+      put_rec((int)((ch + 2) % 3));
+      load_rec(ch + 3);
     }
-    __syncthreads();
-    // weight block: target nw, candidates kg, kg + NW, ...
+    const bool more = ch + 1 < nchunks;
+    const int kofs = 8 * kh;
+    opv_t bop[NS][2];
 #pragma unroll
-    for (int k = kg; k < MK; k += NW) {
-      const double dx = s_c[k][0] - tx, dy = s_c[k][1] - ty, dz = s_c[k][2] - tz;
-      const double c2 = dx * dx + dy * dy + dz * dz;
-      float w = 0.0f;
-      if (c2 <= kp.cs2) {
-        if (KT == 0) w = exp2_neg(chord2_to_d2(c2) * kp.k1);
-        else w = pair_weight(kp, c2, dx, dy, dz, ax, ay, az, bx, by, bz);
-      }
-      const uint16_t whi = to_bits<F16>(w);
-      float wr = from_bits<F16>(whi);
-      s_wt[0][nw * KP + k] = whi;
-      if constexpr (SPLIT) {
-        const uint16_t wlo = to_bits<F16>(w - wr);
-        s_wt[NS - 1][nw * KP + k] = wlo;
-        wr += from_bits<F16>(wlo);
-      }
-      wsum += (double)w;
-      wsum_r += (double)wr;
-    }
-    // data block: items of 4 samples x 4 channels, stored transposed (hi and lo planes)
-    for (int item = t; item < NITEMS; item += NT) {
-      const int rg = item / (CP / 4);
-      const int cc = (item % (CP / 4)) * 4;
-      const int nvalid = (int)((nchan - c0 - cc) < 4 ? (nchan - c0 - cc) : 4);
-      float v[4][4];
+    for (int sp = 0; sp < NS; ++sp)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = s_row[rg * 4 + r];
-        if (row >= 0 && nvalid > 0) load4<T>(data + row + c0 + cc, nvalid, vec_ok, v[r]);
-        else {
+      for (int nb = 0; nb < 2; ++nb)
+        bop[sp][nb] = *reinterpret_cast<const opv_t*>(&s_wt[wc][sp][(nb * 32 + cl) * KP + kofs]);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) v[r][q] = 0.0f;
+    for (int b = 0; b < BPW; ++b) {
+      // this lane's data of chunk ch -> MFMA operands (hi, lo); refill with chunk ch+1
+      opv_t aop[NS];
+      {
+        uint32_t hp[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hp[q] = cvt_pk<F16>(raw[b][2 * q], raw[b][2 * q + 1]);
+        aop[0] = __builtin_bit_cast(opv_t, hp);
+        if constexpr (SPLIT && !BF16IN) {
+          uint32_t lp[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            lp[q] = cvt_pk<F16>(raw[b][2 * q] - unpk_lo<F16>(hp[q]),
+                                raw[b][2 * q + 1] - unpk_hi<F16>(hp[q]));
+          aop[NS - 1] = __builtin_bit_cast(opv_t, lp);
         }
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        uint16_t h[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) h[r] = to_bits<F16>(v[r][j]);
-        uint2 pk;
-        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-        *reinterpret_cast<uint2*>(&s_dt[0][(cc + j) * KP + rg * 4]) = pk;
-        if constexpr (SPLIT) {
-          uint16_t l[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) l[r] = to_bits<F16>(v[r][j] - from_bits<F16>(h[r]));
-          pk.x = (uint32_t)l[0] | ((uint32_t)l[1] << 16);
-          pk.y = (uint32_t)l[2] | ((uint32_t)l[3] << 16);
-          *reinterpret_cast<uint2*>(&s_dt[NS - 1][(cc + j) * KP + rg * 4]) = pk;
-        }
-      }
-    }
-    __syncthreads();
-    // matrix cores: acc[b][nb] (32 channels x 32 targets) += A (32 x 16) * B (16 x 32)
-#pragma unroll
-    for (int ks = 0; ks < MK / 16; ++ks) {
-      const int kofs = ks * 16 + 8 * (lane >> 5);
-      opv_t bop[NS][2];
-#pragma unroll
-      for (int sp = 0; sp < NS; ++sp)
+      if (more) load_block(r1, b);
+      // independent accumulators back to back; the residual products last
+      if constexpr (F16) {
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb)
-          bop[sp][nb] =
-              *reinterpret_cast<const opv_t*>(&s_wt[sp][(nb * 32 + (lane & 31)) * KP + kofs]);
+          acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
+      } else {
 #pragma unroll
-      for (int b = 0; b < BPW; ++b) {
-        const int cb = (wv * BPW + b) * 32;
-        opv_t aop[NS];
+        for (int nb = 0; nb < 2; ++nb)
+          acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
+        if constexpr (SPLIT) {
 #pragma unroll
-        for (int sp = 0; sp < NS; ++sp)
-          aop[sp] = *reinterpret_cast<const opv_t*>(&s_dt[sp][(cb + (lane & 31)) * KP + kofs]);
+          for (int nb = 0; nb < 2; ++nb)
+            acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[1][nb], acc[b][nb], 0, 0, 0);
+          if constexpr (!BF16IN) {
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          if constexpr (F16) {
-            acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
-          } else {
-            acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
-            if constexpr (SPLIT) {
+            for (int nb = 0; nb < 2; ++nb)
               acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[1], bop[0][nb], acc[b][nb], 0, 0, 0);
-              acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[1][nb], acc[b][nb], 0, 0, 0);
-            }
           }
         }
       }
+      // weight block of chunk ch+1, spread over the channel blocks
+      if (more) {
+#pragma unroll
+        for (int k = kg + b * NW; k < MK; k += BPW * NW) weight(r1, wc ^ 1, k);
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // weight sums of each target (8 partial sums per target)
   s_red[0][kg][nw] = wsum;
@@ -293,7 +381,7 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
       }
     }
   }
-  if (blockIdx.y == 0 && t < kTile) {
+  if (pass == 0 && t < kTile) {
     const int64_t slot = tile * kTile + t;
     if (fin) {
       const int32_t tg = ov.slot_target[slot];
@@ -309,50 +397,57 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
 }
 
 template <int NW, int BPW, int MODE, typename T>
-static void launch_cfg(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                       const uint32_t* vals, const void* data, int64_t ld, int64_t nchan,
-                       const OutView& ov, hipStream_t st) {
+static void launch_cfg(const TileView& tv, const KernelParams& kp, const void* data,
+                       const void* zrow, int64_t ld, int64_t nchan, const OutView& ov,
+                       hipStream_t st) {
   constexpr int CP = NW * BPW * 32;
   const int64_t npass = (nchan + CP - 1) / CP;
-  const dim3 g((unsigned)ntiles, (unsigned)npass), b(NW * 64);
-  const int vec_ok = (ld % 4 == 0) && ((uintptr_t)data % (4 * sizeof(T)) == 0) ? 1 : 0;
-  if (kp.type == 0)
-    hipLaunchKernelGGL((k_gather_mfma<NW, BPW, 0, MODE, T>), g, b, 0, st, tv, kp, vals,
-                       (const T*)data, ld, nchan, vec_ok, ov);
-  else
-    hipLaunchKernelGGL((k_gather_mfma<NW, BPW, 1, MODE, T>), g, b, 0, st, tv, kp, vals,
-                       (const T*)data, ld, nchan, vec_ok, ov);
+  const dim3 g((unsigned)(tv.ntiles * npass)), b(NW * 64);
+  const bool full = nchan % CP == 0;
+  const T* d = (const T*)data;
+  const T* z = (const T*)zrow;
+#define CG_MFMA_LAUNCH(KT_, FULL_)                                                              \
+  hipLaunchKernelGGL((k_gather_mfma<NW, BPW, KT_, MODE, FULL_, T>), g, b, 0, st, tv, kp, d, z, \
+                     ld, nchan, ov)
+  if (kp.type == 0) {
+    if (full) CG_MFMA_LAUNCH(0, true);
+    else CG_MFMA_LAUNCH(0, false);
+  } else {
+    if (full) CG_MFMA_LAUNCH(1, true);
+    else CG_MFMA_LAUNCH(1, false);
+  }
+#undef CG_MFMA_LAUNCH
 }
 
 template <int MODE, typename T>
-static void launch_dt(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                      const uint32_t* vals, const void* data, int64_t ld, int64_t nchan,
-                      const OutView& ov, hipStream_t st) {
-  if (nchan <= 64) launch_cfg<2, 1, MODE, T>(tv, kp, ntiles, vals, data, ld, nchan, ov, st);
-  else if (nchan <= 128) launch_cfg<4, 1, MODE, T>(tv, kp, ntiles, vals, data, ld, nchan, ov, st);
-  else if (nchan <= 256) launch_cfg<8, 1, MODE, T>(tv, kp, ntiles, vals, data, ld, nchan, ov, st);
-  else if (nchan <= 512) launch_cfg<8, 2, MODE, T>(tv, kp, ntiles, vals, data, ld, nchan, ov, st);
-  else launch_cfg<8, 4, MODE, T>(tv, kp, ntiles, vals, data, ld, nchan, ov, st);
+static void launch_dt(const TileView& tv, const KernelParams& kp, const void* data,
+                      const void* zrow, int64_t ld, int64_t nchan, const OutView& ov,
+                      hipStream_t st) {
+  if (nchan <= 64) launch_cfg<2, 1, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else if (nchan <= 128) launch_cfg<4, 1, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else if (nchan <= 256) launch_cfg<8, 1, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else if (nchan <= 512) launch_cfg<8, 2, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else launch_cfg<8, 4, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
 }
 
 template <int MODE>
-static void launch_prec(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                        const uint32_t* vals, const void* data, int dtype, int64_t ld,
-                        int64_t nchan, const OutView& ov, hipStream_t st) {
+static void launch_prec(const TileView& tv, const KernelParams& kp, const void* data,
+                        const void* zrow, int dtype, int64_t ld, int64_t nchan,
+                        const OutView& ov, hipStream_t st) {
   switch (dtype) {
-    case 0: launch_dt<MODE, double>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
-    case 1: launch_dt<MODE, float>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
-    case 2: launch_dt<MODE, _Float16>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
-    default: launch_dt<MODE, uint16_t>(tv, kp, ntiles, vals, data, ld, nchan, ov, st); break;
+    case 0: launch_dt<MODE, double>(tv, kp, data, zrow, ld, nchan, ov, st); break;
+    case 1: launch_dt<MODE, float>(tv, kp, data, zrow, ld, nchan, ov, st); break;
+    case 2: launch_dt<MODE, _Float16>(tv, kp, data, zrow, ld, nchan, ov, st); break;
+    default: launch_dt<MODE, uint16_t>(tv, kp, data, zrow, ld, nchan, ov, st); break;
   }
 }
 
-hipError_t launch_gather_mfma(const TileView& tv, const KernelParams& kp, int64_t ntiles,
-                              const uint32_t* vals, const void* data, int dtype, int64_t ld,
-                              int64_t nchan, int prec, const OutView& ov, hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
-  if (prec == 2) launch_prec<1>(tv, kp, ntiles, vals, data, dtype, ld, nchan, ov, st);
-  else launch_prec<0>(tv, kp, ntiles, vals, data, dtype, ld, nchan, ov, st);
+hipError_t launch_gather_mfma(const TileView& tv, const KernelParams& kp, const void* data,
+                              const void* zrow, int dtype, int64_t ld, int64_t nchan, int prec,
+                              const OutView& ov, hipStream_t st) {
+  if (tv.ntiles <= 0) return hipSuccess;
+  if (prec == 2) launch_prec<1>(tv, kp, data, zrow, dtype, ld, nchan, ov, st);
+  else launch_prec<0>(tv, kp, data, zrow, dtype, ld, nchan, ov, st);
   return hipGetLastError();
 }
 

@@ -325,13 +325,18 @@ hipError_t launch_tile_ranges(const double* caps, int64_t ntiles, int64_t nside,
 }
 
 // ---------------------------------------------------------------------------
-// Expand each tile's ranges into its list of sorted-sample positions.
+// Expand each tile's ranges into its list of candidates: sorted position,
+// input index and unit vector, so the contraction reads them in one level.
 
 __global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ range_off,
                                                const uint32_t* __restrict__ ranges,
                                                const uint32_t* __restrict__ nranges,
                                                const uint64_t* __restrict__ cand_off,
-                                               uint32_t* __restrict__ cand) {
+                                               const uint32_t* __restrict__ vals,
+                                               const double* __restrict__ sx, int64_t nsorted,
+                                               uint32_t* __restrict__ cand,
+                                               uint32_t* __restrict__ crow,
+                                               double* __restrict__ cxyz, int64_t ncap) {
   const int64_t tile = blockIdx.x;
   const uint64_t roff = range_off[tile];
   const uint32_t nr = nranges[tile];
@@ -339,16 +344,26 @@ __global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ rang
   for (uint32_t k = 0; k < nr; ++k) {
     const uint32_t b = ranges[2 * (roff + k)];
     const uint32_t len = ranges[2 * (roff + k) + 1];
-    for (uint32_t q = threadIdx.x; q < len; q += 64) cand[out + q] = b + q;
+    for (uint32_t q = threadIdx.x; q < len; q += 64) {
+      const uint32_t pos = b + q;
+      const uint64_t o = out + q;
+      cand[o] = pos;
+      crow[o] = vals[pos];
+      cxyz[o] = sx[pos];
+      cxyz[ncap + o] = sx[nsorted + pos];
+      cxyz[2 * ncap + o] = sx[2 * nsorted + pos];
+    }
     out += len;
   }
 }
 
 hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
-                         const uint64_t* cand_off, int64_t ntiles, uint32_t* cand, hipStream_t st) {
+                         const uint64_t* cand_off, int64_t ntiles, const uint32_t* vals,
+                         const double* sx, int64_t nsorted, uint32_t* cand, uint32_t* crow,
+                         double* cxyz, int64_t ncap, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_expand, dim3((unsigned)ntiles), dim3(64), 0, st, range_off, ranges, nranges,
-                     cand_off, cand);
+                     cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap);
   return hipGetLastError();
 }
 
