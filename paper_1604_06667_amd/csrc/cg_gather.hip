@@ -10,6 +10,11 @@
 
 namespace cg {
 
+__device__ __noinline__ double chord2_to_d2_exact(double c2) {
+  const double d = 2.0 * asin(0.5 * sqrt(c2));
+  return d * d;
+}
+
 constexpr int kChunk = 64;   // candidates staged per step
 
 __device__ __forceinline__ double wsum(double v) {

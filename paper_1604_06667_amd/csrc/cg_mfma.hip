@@ -22,6 +22,11 @@
 
 namespace cg {
 
+__device__ __noinline__ double chord2_to_d2_exact(double c2) {
+  const double d = 2.0 * asin(0.5 * sqrt(c2));
+  return d * d;
+}
+
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
@@ -137,7 +142,7 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
   using opv_t = typename std::conditional<F16, f16x8_t, bf16x8_t>::type;
   __shared__ __attribute__((aligned(16))) uint16_t s_wt[2][NS][kTile * KP];  // [buf][part][target][sample]
   __shared__ double s_c[3][MK][3];
-  __shared__ const T* s_row[3][MK];
+  __shared__ int64_t s_row[3][MK];   // element offset of each candidate's row from data
   __shared__ double s_red[2][NW][kTile];
   __shared__ double s_wfin[2][kTile];
   __shared__ double s_tg[kTile][KT == 1 ? 9 : 3];   // target xyz (+ major, minor axis)
@@ -200,18 +205,19 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
   const int64_t nchunks = (int64_t)((cb1 - cb0 + MK - 1) / MK);
 
   // candidate record of chunk ch for thread t < MK (NaN / zero row past the end)
+  const int64_t zoff = (int64_t)(zrow - data) - c0;   // offset that lands on the zero row
   double rx = nan, ry = nan, rz = nan;
-  const T* rrow = zrow;
+  int64_t rrow = zoff;
   auto load_rec = [&](int64_t ch) {
     const uint64_t q = cb0 + (uint64_t)ch * MK + t;
     if (ch < nchunks && q < cb1) {
       rx = tv.cxyz[q];
       ry = tv.cxyz[cap + q];
       rz = tv.cxyz[2 * cap + q];
-      rrow = data + (int64_t)tv.crow[q] * ld;
+      rrow = (int64_t)tv.crow[q] * ld;
     } else {
       rx = ry = rz = nan;
-      rrow = zrow - c0;   // + channel offsets below stays inside the zero row
+      rrow = zoff;   // + channel offsets below stays inside the zero row
     }
   };
   auto put_rec = [&](int buf) {
@@ -250,7 +256,7 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
   auto load_block = [&](int rb, int b) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const T* p = s_row[rb][8 * kh + i] + cbase + 32 * b;
+      const T* p = data + (s_row[rb][8 * kh + i] + cbase + 32 * b);
       raw[b][i] = bvalid[b] ? in_f32<T>(p) : 0.0f;
     }
   };
@@ -281,7 +287,6 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
       put_rec((int)((ch + 2) % 3));
       load_rec(ch + 3);
     }
-    const bool more = ch + 1 < nchunks;
     const int kofs = 8 * kh;
     opv_t bop[NS][2];
 #pragma unroll
@@ -307,7 +312,7 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
           aop[NS - 1] = __builtin_bit_cast(opv_t, lp);
         }
       }
-      if (more) load_block(r1, b);
+      load_block(r1, b);   // past the last chunk this reads the zero row
       // independent accumulators back to back; the residual products last
       if constexpr (F16) {
 #pragma unroll
@@ -328,11 +333,10 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
           }
         }
       }
-      // weight block of chunk ch+1, spread over the channel blocks
-      if (more) {
+      // weight block of chunk ch+1 (all zero past the last chunk), spread over
+      // the channel blocks
 #pragma unroll
-        for (int k = kg + b * NW; k < MK; k += BPW * NW) weight(r1, wc ^ 1, k);
-      }
+      for (int k = kg + b * NW; k < MK; k += BPW * NW) weight(r1, wc ^ 1, k);
     }
   }
   __syncthreads();
