@@ -217,6 +217,12 @@ cg_status cg_hpx_ring_info(int64_t nside, int64_t i, int64_t* start, int64_t* np
  * max_ranges is too small. */
 cg_status cg_hpx_cap_ranges(int64_t nside, double lon_deg, double lat_deg, double rho_deg,
                             int64_t* ranges, int64_t max_ranges, int64_t* nranges);
+/* Pixel ranges that may hold points within rho_deg of ANY of n points (the
+ * union of their disks, ring by ring: the lookup a tile of n targets uses;
+ * 1 <= n <= 4096); output as for cg_hpx_cap_ranges. */
+cg_status cg_hpx_targets_ranges(int64_t nside, int64_t n, const double* lon_deg,
+                                const double* lat_deg, double rho_deg, int64_t* ranges,
+                                int64_t max_ranges, int64_t* nranges);
 /* WCS pixel centres (host): world coordinates of 1-based pixels (i, j);
  * NaN where the pixel has none. */
 cg_status cg_wcs_pix2world(const cg_wcs* wcs, int64_t n, const double* i, const double* j,

@@ -9,4 +9,4 @@ library.
 """
 from ._cg import (WcsGrid, SlGrid, CgError, lib, version, parse_header,  # noqa: F401
                   hpx_ang2pix_ring, hpx_pix2ang_ring, hpx_pix2ring, hpx_ring_info,
-                  hpx_cap_ranges, wcs_pix2world, PREC, KERNEL)
+                  hpx_cap_ranges, hpx_targets_ranges, wcs_pix2world, PREC, KERNEL)

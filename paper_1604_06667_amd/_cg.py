@@ -61,6 +61,7 @@ SIGNATURES = {
     "cg_hpx_pix2ring": (_i32, [_i64, _i64, _vp, _vp, _vp]),
     "cg_hpx_ring_info": (_i32, [_i64, _i64, _P(_i64), _P(_i64), _P(_d)]),
     "cg_hpx_cap_ranges": (_i32, [_i64, _d, _d, _d, _vp, _i64, _P(_i64)]),
+    "cg_hpx_targets_ranges": (_i32, [_i64, _i64, _vp, _vp, _d, _vp, _i64, _P(_i64)]),
     "cg_wcs_pix2world": (_i32, [_P(CgWcs), _i64, _vp, _vp, _vp, _vp]),
 }
 
@@ -357,6 +358,17 @@ def hpx_cap_ranges(nside, lon_deg, lat_deg, rho_deg, max_ranges=1 << 16):
     n = C.c_int64()
     check(lib().cg_hpx_cap_ranges(int(nside), float(lon_deg), float(lat_deg), float(rho_deg),
                                   _np_ptr(buf), int(max_ranges), C.byref(n)))
+    return buf[: 2 * n.value].reshape(-1, 2)
+
+
+def hpx_targets_ranges(nside, lon_deg, lat_deg, rho_deg, max_ranges=1 << 16):
+    import numpy as np
+    lo = np.ascontiguousarray(lon_deg, dtype=np.float64)
+    la = np.ascontiguousarray(lat_deg, dtype=np.float64)
+    buf = np.empty(2 * max_ranges, dtype=np.int64)
+    n = C.c_int64()
+    check(lib().cg_hpx_targets_ranges(int(nside), lo.shape[0], _np_ptr(lo), _np_ptr(la),
+                                      float(rho_deg), _np_ptr(buf), int(max_ranges), C.byref(n)))
     return buf[: 2 * n.value].reshape(-1, 2)
 
 

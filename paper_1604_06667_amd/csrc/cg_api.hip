@@ -193,8 +193,9 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
   CG_HIP(cg::launch_permute(g->sorted_vals, roff + 4 * nside, n, lon, lat, data, dtype, ld,
                             g->nchan, with_data, n, g->sx.as<double>(), g->sdata.as<float>(), st),
          "permute");
-  CG_HIP(cg::launch_tile_ranges(g->caps.as<double>(), g->ntiles, nside, g->support_rad + 1e-9,
-                                g->ring_first.as<int32_t>(), g->range_off.as<uint64_t>(),
+  CG_HIP(cg::launch_tile_ranges(g->caps.as<double>(), g->txyz.as<double>(), g->nslots, g->ntiles,
+                                nside, g->support_rad + 1e-9, g->ring_first.as<int32_t>(),
+                                g->range_off.as<uint64_t>(),
                                 g->sorted_keys, roff, g->ranges.as<uint32_t>(),
                                 g->nranges.as<uint32_t>(), g->ncand.as<uint64_t>(), st),
          "tile ranges");
@@ -698,6 +699,49 @@ cg_status cg_hpx_cap_ranges(int64_t nside, double lon_deg, double lat_deg, doubl
   for (int64_t i = f; i <= l; ++i) {
     int64_t lo[2], hi[2];
     const int nr = cg::hpx::ring_cap_ranges(nside, i, cz, cs, cphi, rho, lo, hi);
+    for (int q = 0; q < nr; ++q) {
+      if (k >= max_ranges) return fail(CG_E_INVALID, "max_ranges too small");
+      ranges[2 * k] = lo[q];
+      ranges[2 * k + 1] = hi[q];
+      ++k;
+    }
+  }
+  *nranges = k;
+  return CG_OK;
+}
+
+cg_status cg_hpx_targets_ranges(int64_t nside, int64_t n, const double* lon_deg,
+                                const double* lat_deg, double rho_deg, int64_t* ranges,
+                                int64_t max_ranges, int64_t* nranges) {
+  if (nside < 1 || nside > 8192 || n < 1 || n > 4096 || !lon_deg || !lat_deg || !ranges ||
+      !nranges || !(rho_deg >= 0.0))
+    return fail(CG_E_INVALID, "bad arguments");
+  const double rho = rho_deg * kDeg;
+  std::vector<cg::hpx::DiskPrep> d((size_t)n);
+  std::vector<double> rel((size_t)n);
+  // reference longitude: the first point's
+  double ref = 0.0;
+  int64_t f = 4 * nside, l = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    double am = fmod(lon_deg[k], 360.0);
+    if (am < 0.0) am += 360.0;
+    const double phi = am * kDeg, la = lat_deg[k] * kDeg;
+    if (k == 0) ref = phi;
+    cg::hpx::disk_prepare(sin(la), cos(la), rho, &d[(size_t)k]);
+    rel[(size_t)k] = cg::hpx::rel_lon(phi, ref);
+    int64_t a, b;
+    cg::hpx::cap_ring_span(nside, sin(la), cos(la), rho, &a, &b);
+    if (a < f) f = a;
+    if (b > l) l = b;
+  }
+  int64_t k = 0;
+  for (int64_t i = f; i <= l; ++i) {
+    double plo, phi;
+    int full;
+    if (!cg::hpx::ring_union_window(nside, i, d.data(), rel.data(), (int)n, ref, &plo, &phi, &full))
+      continue;
+    int64_t lo[2], hi[2];
+    const int nr = cg::hpx::ring_window_ranges(nside, i, plo, phi, full, lo, hi);
     for (int q = 0; q < nr; ++q) {
       if (k >= max_ranges) return fail(CG_E_INVALID, "max_ranges too small");
       ranges[2 * k] = lo[q];

@@ -133,7 +133,8 @@ hipError_t launch_tile_caps(const double* txyz, int64_t nslots, int64_t ntiles, 
                             hipStream_t st);
 hipError_t launch_tile_span(const double* caps, int64_t ntiles, int64_t nside, double rho_extra,
                             int32_t* ring_first, uint64_t* span_bound, hipStream_t st);
-hipError_t launch_tile_ranges(const double* caps, int64_t ntiles, int64_t nside, double rho_extra,
+hipError_t launch_tile_ranges(const double* caps, const double* txyz, int64_t nslots,
+                              int64_t ntiles, int64_t nside, double rho,
                               const int32_t* ring_first, const uint64_t* range_off,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st);

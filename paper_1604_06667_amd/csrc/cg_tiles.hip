@@ -246,7 +246,13 @@ hipError_t launch_tile_span(const double* caps, int64_t ntiles, int64_t nside, d
 }
 
 // ---------------------------------------------------------------------------
-// Candidate ranges: one wavefront per tile, one ring per lane.
+// Candidate ranges: one wavefront per tile.  For each ring crossing the
+// tile's widened cap, the longitude window is the union over the tile's
+// targets of the window of each target's own support disk (lane = target,
+// wavefront min/max), which is tighter than the window of the cap around
+// the whole tile.  The windows of a batch of rings are collected in LDS, then
+// one ring per lane turns them into pixel ranges and two binary searches in
+// the ring's sorted segment give the sample ranges.
 
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, uint32_t lo,
                                                     uint32_t hi, uint64_t v) {
@@ -258,55 +264,106 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
   return lo;
 }
 
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+constexpr int kRingBatch = 256;
+
 __global__ void __launch_bounds__(64) k_tile_ranges(
-    const double* __restrict__ caps, int64_t nside, double rho_extra,
-    const int32_t* __restrict__ ring_first, const uint64_t* __restrict__ range_off,
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ring_off,
-    uint32_t* __restrict__ ranges, uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
+    const double* __restrict__ caps, const double* __restrict__ txyz, int64_t nslots,
+    int64_t nside, double rho, const int32_t* __restrict__ ring_first,
+    const uint64_t* __restrict__ range_off, const uint32_t* __restrict__ keys,
+    const uint32_t* __restrict__ ring_off, uint32_t* __restrict__ ranges,
+    uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
+  __shared__ double s_lo[kRingBatch], s_hi[kRingBatch];
+  __shared__ int s_st[kRingBatch];
   const int64_t tile = blockIdx.x;
   const int lane = threadIdx.x;
   const uint64_t off = range_off[tile];
   const int64_t nring = (int64_t)((range_off[tile + 1] - off) / 2);
   double cz, cs, cphi, r;
   cap_angles(caps, tile, &cz, &cs, &cphi, &r);
-  const double rho = r + rho_extra;
+  // this lane's target disk
+  const int64_t slot = tile * kTile + lane;
+  const double x = txyz[slot], y = txyz[nslots + slot], z = txyz[2 * nslots + slot];
+  const bool valid = isfinite(x);
+  hpx::DiskPrep dp;
+  double rel = 0.0;
+  if (valid) {
+    hpx::disk_prepare(z, sqrt(x * x + y * y), rho, &dp);
+    double p = atan2(y, x);
+    if (p < 0.0) p += hpx::kTwoPi;
+    rel = hpx::rel_lon(p, cphi);
+  }
   const int64_t f = ring_first[tile];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t written = 0;
   uint64_t total = 0;
-  for (int64_t base = 0; base < nring; base += 64) {
-    const int64_t i = f + base + lane;
-    uint32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
-    if (base + lane < nring) {
-      int64_t lo[2], hi[2];
-      const int nr = hpx::ring_cap_ranges(nside, i, cz, cs, cphi, rho, lo, hi);
-      const uint32_t rb = ring_off[i], re = ring_off[i + 1];
-      if (re > rb) {
-        if (nr >= 1) {
-          b0 = lower_bound_u32(keys, rb, re, (uint64_t)lo[0]);
-          e0 = lower_bound_u32(keys, b0, re, (uint64_t)hi[0] + 1);
-        }
-        if (nr >= 2) {
-          b1 = lower_bound_u32(keys, rb, re, (uint64_t)lo[1]);
-          e1 = lower_bound_u32(keys, b1, re, (uint64_t)hi[1] + 1);
+  for (int64_t b0 = 0; b0 < nring; b0 += kRingBatch) {
+    const int nb = (int)((nring - b0) < kRingBatch ? (nring - b0) : kRingBatch);
+    for (int q = 0; q < nb; ++q) {
+      const int64_t i = f + b0 + q;
+      int st = 0;
+      double lo = 1e300, hi = -1e300;
+      if (valid) {
+        double w;
+        st = hpx::ring_disk_halfwidth(nside, i, dp, &w);
+        if (st == 1) {
+          lo = rel - w;
+          hi = rel + w;
         }
       }
+      const bool anyfull = __ballot(st == 2) != 0;
+      const bool anywin = __ballot(st == 1) != 0;
+      lo = wave_min(lo);
+      hi = wave_max(hi);
+      if (lane == 0) {
+        int code = 0;
+        if (anyfull || (anywin && hi - lo >= hpx::kTwoPi)) code = 2;
+        else if (anywin) code = 1;
+        s_st[q] = code;
+        s_lo[q] = cphi + lo;
+        s_hi[q] = cphi + hi;
+      }
     }
-    const bool h0 = e0 > b0, h1 = e1 > b1;
-    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
-    const uint32_t pos = (uint32_t)(__popcll(m0 & lt) + __popcll(m1 & lt));
-    uint32_t k = written + pos;
-    if (h0) {
-      ranges[2 * (off + k) + 0] = b0;
-      ranges[2 * (off + k) + 1] = e0 - b0;
-      ++k;
+    __syncthreads();
+    for (int qb = 0; qb < nb; qb += 64) {
+      const int q = qb + lane;
+      uint32_t b0r = 0, e0 = 0, b1 = 0, e1 = 0;
+      if (q < nb && s_st[q] != 0) {
+        const int64_t i = f + b0 + q;
+        int64_t plo[2], phi[2];
+        const int nr = hpx::ring_window_ranges(nside, i, s_lo[q], s_hi[q], s_st[q] == 2, plo, phi);
+        const uint32_t rb = ring_off[i], re = ring_off[i + 1];
+        if (re > rb) {
+          b0r = lower_bound_u32(keys, rb, re, (uint64_t)plo[0]);
+          e0 = lower_bound_u32(keys, b0r, re, (uint64_t)phi[0] + 1);
+          if (nr >= 2) {
+            b1 = lower_bound_u32(keys, rb, re, (uint64_t)plo[1]);
+            e1 = lower_bound_u32(keys, b1, re, (uint64_t)phi[1] + 1);
+          }
+        }
+      }
+      const bool h0 = e0 > b0r, h1 = e1 > b1;
+      const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+      const uint32_t pos = (uint32_t)(__popcll(m0 & lt) + __popcll(m1 & lt));
+      uint32_t k = written + pos;
+      if (h0) {
+        ranges[2 * (off + k) + 0] = b0r;
+        ranges[2 * (off + k) + 1] = e0 - b0r;
+        ++k;
+      }
+      if (h1) {
+        ranges[2 * (off + k) + 0] = b1;
+        ranges[2 * (off + k) + 1] = e1 - b1;
+      }
+      written += (uint32_t)(__popcll(m0) + __popcll(m1));
+      total += (uint64_t)wave_sum((double)((h0 ? e0 - b0r : 0u) + (h1 ? e1 - b1 : 0u)));
     }
-    if (h1) {
-      ranges[2 * (off + k) + 0] = b1;
-      ranges[2 * (off + k) + 1] = e1 - b1;
-    }
-    written += (uint32_t)(__popcll(m0) + __popcll(m1));
-    total += (uint64_t)wave_sum((double)((h0 ? e0 - b0 : 0u) + (h1 ? e1 - b1 : 0u)));
+    __syncthreads();
   }
   if (lane == 0) {
     nranges[tile] = written;
@@ -314,13 +371,14 @@ __global__ void __launch_bounds__(64) k_tile_ranges(
   }
 }
 
-hipError_t launch_tile_ranges(const double* caps, int64_t ntiles, int64_t nside, double rho_extra,
+hipError_t launch_tile_ranges(const double* caps, const double* txyz, int64_t nslots,
+                              int64_t ntiles, int64_t nside, double rho,
                               const int32_t* ring_first, const uint64_t* range_off,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ntiles), dim3(64), 0, st, caps, nside,
-                     rho_extra, ring_first, range_off, keys, ring_off, ranges, nranges, ncand);
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ntiles), dim3(64), 0, st, caps, txyz, nslots,
+                     nside, rho, ring_first, range_off, keys, ring_off, ranges, nranges, ncand);
   return hipGetLastError();
 }
 

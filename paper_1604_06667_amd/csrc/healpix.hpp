@@ -219,6 +219,135 @@ CG_HD int ring_cap_ranges(int64_t nside, int64_t i, double cz, double cs, double
   return 1;
 }
 
+// One disk of angular radius rho around a point, prepared for the per-ring
+// lookup (the quantities below depend only on the point and rho).
+struct DiskPrep {
+  double tz, ts;        // cos and sin of the colatitude of the centre
+  double zmin, zmax;    // latitude band of the disk (z = cos theta)
+  double crho, zstar;   // cos(rho); z at which the disk is widest in longitude
+  int all;              // rho >= pi/2: every ring may be fully inside
+};
+
+CG_HD void disk_prepare(double tz, double ts, double rho, DiskPrep* d) {
+  const double th = atan2(ts, tz);
+  d->tz = tz;
+  d->ts = ts;
+  d->zmax = (th - rho <= 0.0) ? 1.0 : cos(th - rho);
+  d->zmin = (th + rho >= kPi) ? -1.0 : cos(th + rho);
+  d->crho = cos(rho);
+  d->all = rho >= kHalfPi;
+  d->zstar = d->all ? 0.0 : tz / d->crho;
+}
+
+// Half-width in longitude of the part of ring i that can lie within the
+// disk: the same bound as in ring_cap_ranges.  Returns 0 when the ring's
+// latitude extent misses the disk, 2 when the whole ring may be inside
+// (*dphi untouched), else 1 with the half-width in *dphi.
+CG_HD int ring_disk_halfwidth(int64_t nside, int64_t i, const DiskPrep& d, double* dphi) {
+  const double eps = 1e-12;
+  const double zl = ring_z(nside, i + 1) - eps;
+  const double zh = ring_z(nside, i - 1) + eps;
+  const double a = zl > d.zmin ? zl : d.zmin;
+  const double b = zh < d.zmax ? zh : d.zmax;
+  if (a > b) return 0;
+  if (d.all) return 2;
+  double zs = d.zstar;
+  zs = zs < a ? a : (zs > b ? b : zs);
+  const double sz = sqrt(fmax(0.0, (1.0 - zs) * (1.0 + zs)));
+  const double den = sz * d.ts;
+  if (den <= 0.0) return 2;
+  const double arg = (d.crho - zs * d.tz) / den;
+  if (arg <= -1.0) return 2;
+  *dphi = (arg >= 1.0) ? 0.0 : acos(arg);
+  return 1;
+}
+
+// Longitude of a point relative to a reference longitude, in (-pi, pi].
+CG_HD double rel_lon(double phi, double ref) {
+  double r = phi - ref;
+  if (r > kPi) r -= kTwoPi;
+  if (r <= -kPi) r += kTwoPi;
+  return r;
+}
+
+// Union over a set of disks of their longitude windows on ring i, as one
+// window [*plo, *phi] (absolute longitudes, possibly outside [0, 2 pi)) or
+// the whole ring (*full).  rel[k] is the centre longitude of disk k relative
+// to ref.  Returns 0 when no disk meets the ring.  The kernels form the same
+// union with one disk per lane and wavefront reductions.
+CG_HD int ring_union_window(int64_t nside, int64_t i, const DiskPrep* d, const double* rel,
+                            int n, double ref, double* plo, double* phi, int* full) {
+  double lo = 1e300, hi = -1e300;
+  int any = 0, f = 0;
+  for (int k = 0; k < n; ++k) {
+    double w;
+    const int r = ring_disk_halfwidth(nside, i, d[k], &w);
+    if (r == 2) f = 1;
+    if (r == 1) {
+      any = 1;
+      lo = fmin(lo, rel[k] - w);
+      hi = fmax(hi, rel[k] + w);
+    }
+  }
+  if (!any && !f) return 0;
+  if (f || hi - lo >= kTwoPi) {
+    *full = 1;
+  } else {
+    *full = 0;
+    *plo = ref + lo;
+    *phi = ref + hi;
+  }
+  return 1;
+}
+
+// Longitude offset, in pixel widths, of the first pixel centre of ring i:
+// one half in the polar caps and on every other equatorial ring, else 0.
+CG_HD double ring_phase(int64_t nside, int64_t i) {
+  if (i < nside || i > 3 * nside) return 0.5;
+  return ((i - nside) & 1) ? 0.0 : 0.5;
+}
+
+// Pixel ranges of ring i covering the longitude window [plo, phi] (plo may
+// be negative and phi beyond 2 pi; phi - plo < 2 pi).  Pixel j of a ring
+// with n pixels and phase s covers longitudes within
+// [j + s - 1/2, j + s + 1/2] * 2 pi / n at every latitude of the ring (in the
+// polar caps the pixel index is the floor of the scaled longitude; in the
+// equatorial belt the pixel edges run diagonally between the vertices at the
+// centre longitude +- half a pixel), so j is kept when that interval meets
+// the window, with 1e-6 pixel of slack for rounding.  full != 0 selects the
+// whole ring.
+CG_HD int ring_window_ranges(int64_t nside, int64_t i, double plo, double phi, int full,
+                             int64_t lo[2], int64_t hi[2]) {
+  const int64_t n = ring_npix(nside, i);
+  const int64_t s0 = ring_start(nside, i);
+  if (!full) {
+    const double scale = (double)n / kTwoPi;
+    const double ph = ring_phase(nside, i);
+    const int64_t jl = (int64_t)ceil(plo * scale - ph - 0.5 - 1e-6);
+    const int64_t jh = (int64_t)floor(phi * scale - ph + 0.5 + 1e-6);
+    if (jh - jl + 1 < n) {
+      // bring jl into [0, n)
+      int64_t sh = 0;
+      if (jl < 0) sh = ((-jl) / n + 1) * n;
+      else if (jl >= n) sh = -(jl / n) * n;
+      const int64_t a = jl + sh, b = jh + sh;
+      if (b < n) {
+        lo[0] = s0 + a;
+        hi[0] = s0 + b;
+        return 1;
+      }
+      lo[0] = s0 + a;
+      hi[0] = s0 + n - 1;
+      lo[1] = s0;
+      hi[1] = s0 + (b - n);
+      return 2;
+    }
+  }
+  lo[0] = s0;
+  hi[0] = s0 + n - 1;
+  return 1;
+}
+
 // Rings whose pixels can meet a cap of radius rho around colatitude thc:
 // [first, last], clamped to [1, 4 nside - 1].  Conservative by two rings.
 CG_HD void cap_ring_span(int64_t nside, double cz, double cs, double rho,

@@ -93,6 +93,15 @@ def test_ring_latitude_and_pixel_longitude_extent(nside):
     # pixel j covers longitudes within [j - 1/2, j + 1] (mod n)
     d = (x - j + n / 2.0) % n - n / 2.0
     assert np.all(d >= -0.5 - 1e-9) and np.all(d <= 1.0 + 1e-9)
+    # ... and, tighter, within half a pixel of its centre longitude, whose
+    # phase is 1/2 in the caps and alternates 1/2, 0 along the belt
+    clon, _ = cgp.hpx_pix2ang_ring(nside, pix)
+    c = np.radians(clon) * n / (2 * math.pi)
+    ph = np.where((ring < nside) | (ring > 3 * nside), 0.5,
+                  np.where((ring - nside) % 2 == 0, 0.5, 0.0))
+    assert np.allclose((c - j), ph, atol=1e-9)
+    dc = (x - c + n / 2.0) % n - n / 2.0
+    assert np.all(np.abs(dc) <= 0.5 + 1e-9)
 
 
 def _brute_pix_within(nside, lon0, lat0, rho, g, n=60_000):
@@ -132,3 +141,47 @@ def test_cap_ranges_superset(nside, cap):
     k = np.searchsorted(lo, pix, side="right") - 1
     inside = (k >= 0) & (pix <= hi[np.maximum(k, 0)])
     assert inside.all(), f"{(~inside).sum()} pixels of in-cap points missed"
+
+
+def _coverage(rng, pix):
+    lo, hi = rng[:, 0], rng[:, 1]
+    order = np.argsort(lo)
+    lo, hi = lo[order], hi[order]
+    k = np.searchsorted(lo, pix, side="right") - 1
+    return (k >= 0) & (pix <= hi[np.maximum(k, 0)])
+
+
+# 8x8 target patches: (centre lon, centre lat, spacing deg, support deg)
+PATCHES = [(10.0, 20.0, 0.02, 0.075), (359.95, -5.0, 0.02, 0.075), (120.0, 89.9, 0.01, 0.05),
+           (200.0, -89.93, 0.005, 0.04), (45.0, 41.81, 0.05, 0.2), (300.0, 0.0, 1.0, 3.0),
+           (0.0, 60.0, 5.0, 20.0)]
+
+
+@pytest.mark.parametrize("nside", [4, 256, 8192])
+@pytest.mark.parametrize("patch", PATCHES, ids=lambda c: f"{c[0]}_{c[1]}_{c[2]}")
+def test_targets_ranges_superset(nside, patch):
+    """Union of per-target disks (the tile lookup) covers every pixel of every
+    in-support point of every target, and is no wider than the cap lookup."""
+    lon0, lat0, dx, rho_deg = patch
+    g = np.random.default_rng(int(nside * 3 + lat0 * 7 + dx * 1000) & 0xFFFF)
+    ii, jj = np.meshgrid(np.arange(8) - 3.5, np.arange(8) - 3.5)
+    lat = np.clip(lat0 + jj.ravel() * dx, -90.0, 90.0)
+    lon = (lon0 + ii.ravel() * dx / max(np.cos(np.radians(lat0)), 0.05)) % 360.0
+    rng = cgp.hpx_targets_ranges(nside, lon, lat, rho_deg)
+    assert np.all(rng[:, 1] >= rng[:, 0])
+    for k in range(0, 64, 9):
+        pix = _brute_pix_within(nside, lon[k], lat[k], math.radians(rho_deg), g, n=20_000)
+        assert pix.size > 0
+        inside = _coverage(rng, pix)
+        assert inside.all(), f"target {k}: {(~inside).sum()} pixels missed"
+    # no wider than one cap around all targets
+    c = np.stack([np.cos(np.radians(lat)) * np.cos(np.radians(lon)),
+                  np.cos(np.radians(lat)) * np.sin(np.radians(lon)), np.sin(np.radians(lat))], 1)
+    m = c.mean(0)
+    m /= np.linalg.norm(m)
+    r = np.degrees(np.max(np.arccos(np.clip(c @ m, -1, 1))))
+    cap = cgp.hpx_cap_ranges(nside, math.degrees(math.atan2(m[1], m[0])) % 360.0,
+                             math.degrees(math.asin(m[2])), r + rho_deg + 1e-9)
+    npix_t = int((rng[:, 1] - rng[:, 0] + 1).sum())
+    npix_c = int((cap[:, 1] - cap[:, 0] + 1).sum())
+    assert npix_t <= npix_c
