@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
-    ap.add_argument("--cpu-block", type=int, default=256)
+    ap.add_argument("--cpu-block", type=int, default=384)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()

@@ -246,13 +246,16 @@ hipError_t launch_tile_span(const double* caps, int64_t ntiles, int64_t nside, d
 }
 
 // ---------------------------------------------------------------------------
-// Candidate ranges: one wavefront per tile.  For each ring crossing the
-// tile's widened cap, the longitude window is the union over the tile's
-// targets of the window of each target's own support disk (lane = target,
-// wavefront min/max), which is tighter than the window of the cap around
-// the whole tile.  The windows of a batch of rings are collected in LDS, then
-// one ring per lane turns them into pixel ranges and two binary searches in
-// the ring's sorted segment give the sample ranges.
+// Candidate ranges: one 256-thread block per tile.  For each ring crossing
+// the tile's widened cap, the longitude window is the union over the tile's
+// targets of the window of each target's own support disk, which is tighter
+// than the window of the cap around the whole tile.  The targets' disks are
+// prepared once into LDS.  Rings are taken 256 at a time: first each
+// wavefront forms, for every ring of the batch, the union over its quarter of
+// the targets; then one thread per ring merges the four partial windows,
+// turns the window into pixel ranges, finds the sample ranges with two binary
+// searches in the ring's sorted segment and writes them at positions given by
+// a block-wide scan, in ring order.
 
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, uint32_t lo,
                                                     uint32_t hi, uint64_t v) {
@@ -264,108 +267,129 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
   return lo;
 }
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
+constexpr int kRangeThreads = 256;
+constexpr int kRangeWaves = kRangeThreads / 64;
 
-constexpr int kRingBatch = 256;
-
-__global__ void __launch_bounds__(64) k_tile_ranges(
+__global__ void __launch_bounds__(kRangeThreads) k_tile_ranges(
     const double* __restrict__ caps, const double* __restrict__ txyz, int64_t nslots,
     int64_t nside, double rho, const int32_t* __restrict__ ring_first,
     const uint64_t* __restrict__ range_off, const uint32_t* __restrict__ keys,
     const uint32_t* __restrict__ ring_off, uint32_t* __restrict__ ranges,
     uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
-  __shared__ double s_lo[kRingBatch], s_hi[kRingBatch];
-  __shared__ int s_st[kRingBatch];
+  __shared__ hpx::DiskPrep s_dp[kTile];
+  __shared__ double s_rel[kTile];
+  __shared__ double s_lo[kRangeWaves][kRangeThreads], s_hi[kRangeWaves][kRangeThreads];
+  __shared__ int s_fl[kRangeWaves][kRangeThreads];
+  __shared__ uint32_t s_wsum[kRangeWaves];
+  __shared__ uint64_t s_wcnt[kRangeWaves];
   const int64_t tile = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t off = range_off[tile];
   const int64_t nring = (int64_t)((range_off[tile + 1] - off) / 2);
   double cz, cs, cphi, r;
   cap_angles(caps, tile, &cz, &cs, &cphi, &r);
-  // this lane's target disk
-  const int64_t slot = tile * kTile + lane;
-  const double x = txyz[slot], y = txyz[nslots + slot], z = txyz[2 * nslots + slot];
-  const bool valid = isfinite(x);
-  hpx::DiskPrep dp;
-  double rel = 0.0;
-  if (valid) {
-    hpx::disk_prepare(z, sqrt(x * x + y * y), rho, &dp);
-    double p = atan2(y, x);
-    if (p < 0.0) p += hpx::kTwoPi;
-    rel = hpx::rel_lon(p, cphi);
+  if (tid < kTile) {
+    const int64_t slot = tile * kTile + tid;
+    const double x = txyz[slot], y = txyz[nslots + slot], z = txyz[2 * nslots + slot];
+    hpx::DiskPrep dp;
+    double rel = 0.0;
+    if (isfinite(x)) {
+      hpx::disk_prepare(z, sqrt(x * x + y * y), rho, &dp);
+      double p = atan2(y, x);
+      if (p < 0.0) p += hpx::kTwoPi;
+      rel = hpx::rel_lon(p, cphi);
+    } else {
+      // padding slot: an empty latitude band meets no ring
+      dp.tz = 1.0; dp.ts = 0.0; dp.zmin = 2.0; dp.zmax = -2.0;
+      dp.crho = 1.0; dp.zstar = 0.0; dp.all = 0;
+    }
+    s_dp[tid] = dp;
+    s_rel[tid] = rel;
   }
+  __syncthreads();
   const int64_t f = ring_first[tile];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  constexpr int kPer = kTile / kRangeWaves;
   uint32_t written = 0;
   uint64_t total = 0;
-  for (int64_t b0 = 0; b0 < nring; b0 += kRingBatch) {
-    const int nb = (int)((nring - b0) < kRingBatch ? (nring - b0) : kRingBatch);
-    for (int q = 0; q < nb; ++q) {
-      const int64_t i = f + b0 + q;
-      int st = 0;
+  for (int64_t q0 = 0; q0 < nring; q0 += kRangeThreads) {
+    const int nb = (int)((nring - q0) < kRangeThreads ? (nring - q0) : kRangeThreads);
+    // partial unions: wavefront `wave` covers targets [wave*kPer, (wave+1)*kPer)
+    for (int q = lane; q < nb; q += 64) {
+      double zl, zh;
+      hpx::ring_band(nside, f + q0 + q, &zl, &zh);
       double lo = 1e300, hi = -1e300;
-      if (valid) {
+      int fl = 0;
+      for (int t = wave * kPer; t < (wave + 1) * kPer; ++t) {
+        const hpx::DiskPrep dp = s_dp[t];
         double w;
-        st = hpx::ring_disk_halfwidth(nside, i, dp, &w);
+        const int st = hpx::band_disk_halfwidth(zl, zh, dp, &w);
+        if (st == 2) fl |= 2;
         if (st == 1) {
-          lo = rel - w;
-          hi = rel + w;
+          fl |= 1;
+          lo = fmin(lo, s_rel[t] - w);
+          hi = fmax(hi, s_rel[t] + w);
         }
       }
-      const bool anyfull = __ballot(st == 2) != 0;
-      const bool anywin = __ballot(st == 1) != 0;
-      lo = wave_min(lo);
-      hi = wave_max(hi);
-      if (lane == 0) {
-        int code = 0;
-        if (anyfull || (anywin && hi - lo >= hpx::kTwoPi)) code = 2;
-        else if (anywin) code = 1;
-        s_st[q] = code;
-        s_lo[q] = cphi + lo;
-        s_hi[q] = cphi + hi;
-      }
+      s_lo[wave][q] = lo;
+      s_hi[wave][q] = hi;
+      s_fl[wave][q] = fl;
     }
     __syncthreads();
-    for (int qb = 0; qb < nb; qb += 64) {
-      const int q = qb + lane;
-      uint32_t b0r = 0, e0 = 0, b1 = 0, e1 = 0;
-      if (q < nb && s_st[q] != 0) {
-        const int64_t i = f + b0 + q;
+    uint32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    if (tid < nb) {
+      const int64_t i = f + q0 + tid;
+      double lo = 1e300, hi = -1e300;
+      int fl = 0;
+#pragma unroll
+      for (int w = 0; w < kRangeWaves; ++w) {
+        lo = fmin(lo, s_lo[w][tid]);
+        hi = fmax(hi, s_hi[w][tid]);
+        fl |= s_fl[w][tid];
+      }
+      const int full = (fl & 2) || ((fl & 1) && hi - lo >= hpx::kTwoPi);
+      if (fl) {
         int64_t plo[2], phi[2];
-        const int nr = hpx::ring_window_ranges(nside, i, s_lo[q], s_hi[q], s_st[q] == 2, plo, phi);
+        const int nr = hpx::ring_window_ranges(nside, i, cphi + lo, cphi + hi, full, plo, phi);
         const uint32_t rb = ring_off[i], re = ring_off[i + 1];
         if (re > rb) {
-          b0r = lower_bound_u32(keys, rb, re, (uint64_t)plo[0]);
-          e0 = lower_bound_u32(keys, b0r, re, (uint64_t)phi[0] + 1);
+          b0 = lower_bound_u32(keys, rb, re, (uint64_t)plo[0]);
+          e0 = lower_bound_u32(keys, b0, re, (uint64_t)phi[0] + 1);
           if (nr >= 2) {
             b1 = lower_bound_u32(keys, rb, re, (uint64_t)plo[1]);
             e1 = lower_bound_u32(keys, b1, re, (uint64_t)phi[1] + 1);
           }
         }
       }
-      const bool h0 = e0 > b0r, h1 = e1 > b1;
-      const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
-      const uint32_t pos = (uint32_t)(__popcll(m0 & lt) + __popcll(m1 & lt));
-      uint32_t k = written + pos;
-      if (h0) {
-        ranges[2 * (off + k) + 0] = b0r;
-        ranges[2 * (off + k) + 1] = e0 - b0r;
-        ++k;
-      }
-      if (h1) {
-        ranges[2 * (off + k) + 0] = b1;
-        ranges[2 * (off + k) + 1] = e1 - b1;
-      }
-      written += (uint32_t)(__popcll(m0) + __popcll(m1));
-      total += (uint64_t)wave_sum((double)((h0 ? e0 - b0r : 0u) + (h1 ? e1 - b1 : 0u)));
+    }
+    const bool h0 = e0 > b0, h1 = e1 > b1;
+    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+    const uint32_t wcount = (uint32_t)(__popcll(m0) + __popcll(m1));
+    const double wc = wave_sum((double)((h0 ? e0 - b0 : 0u) + (h1 ? e1 - b1 : 0u)));
+    if (lane == 0) {
+      s_wsum[wave] = wcount;
+      s_wcnt[wave] = (uint64_t)wc;
+    }
+    __syncthreads();
+    uint32_t base = written;
+    for (int w = 0; w < wave; ++w) base += s_wsum[w];
+    uint32_t k = base + (uint32_t)(__popcll(m0 & lt) + __popcll(m1 & lt));
+    if (h0) {
+      ranges[2 * (off + k) + 0] = b0;
+      ranges[2 * (off + k) + 1] = e0 - b0;
+      ++k;
+    }
+    if (h1) {
+      ranges[2 * (off + k) + 0] = b1;
+      ranges[2 * (off + k) + 1] = e1 - b1;
+    }
+    for (int w = 0; w < kRangeWaves; ++w) {
+      written += s_wsum[w];
+      total += s_wcnt[w];
     }
     __syncthreads();
   }
-  if (lane == 0) {
+  if (tid == 0) {
     nranges[tile] = written;
     ncand[tile] = total;
   }
@@ -377,7 +401,8 @@ hipError_t launch_tile_ranges(const double* caps, const double* txyz, int64_t ns
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ntiles), dim3(64), 0, st, caps, txyz, nslots,
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ntiles), dim3(kRangeThreads), 0, st, caps,
+                     txyz, nslots,
                      nside, rho, ring_first, range_off, keys, ring_off, ranges, nranges, ncand);
   return hipGetLastError();
 }
@@ -395,23 +420,50 @@ __global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ rang
                                                uint32_t* __restrict__ cand,
                                                uint32_t* __restrict__ crow,
                                                double* __restrict__ cxyz, int64_t ncap) {
+  // One wavefront per tile.  Ranges are taken 64 at a time (one per lane);
+  // a wavefront scan of their lengths places them, then every lane writes
+  // one candidate per step, finding its range by binary search in LDS.
+  __shared__ uint32_t s_start[64], s_b[64];
   const int64_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
   const uint64_t roff = range_off[tile];
   const uint32_t nr = nranges[tile];
   uint64_t out = cand_off[tile];
-  for (uint32_t k = 0; k < nr; ++k) {
-    const uint32_t b = ranges[2 * (roff + k)];
-    const uint32_t len = ranges[2 * (roff + k) + 1];
-    for (uint32_t q = threadIdx.x; q < len; q += 64) {
-      const uint32_t pos = b + q;
-      const uint64_t o = out + q;
+  for (uint32_t k0 = 0; k0 < nr; k0 += 64) {
+    const uint32_t k = k0 + lane;
+    uint32_t b = 0, len = 0;
+    if (k < nr) {
+      b = ranges[2 * (roff + k)];
+      len = ranges[2 * (roff + k) + 1];
+    }
+    uint32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const uint32_t tot = __shfl(incl, 63, 64);
+    s_start[lane] = incl - len;
+    s_b[lane] = b;
+    __syncthreads();
+    for (uint32_t p = lane; p < tot; p += 64) {
+      // last range whose start is <= p (lengths of the ranges are > 0)
+      int lo = 0, hi = 63;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= p) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint32_t pos = s_b[lo] + (p - s_start[lo]);
+      const uint64_t o = out + p;
       cand[o] = pos;
       crow[o] = vals[pos];
       cxyz[o] = sx[pos];
       cxyz[ncap + o] = sx[nsorted + pos];
       cxyz[2 * ncap + o] = sx[2 * nsorted + pos];
     }
-    out += len;
+    out += tot;
+    __syncthreads();
   }
 }
 

@@ -239,14 +239,11 @@ CG_HD void disk_prepare(double tz, double ts, double rho, DiskPrep* d) {
   d->zstar = d->all ? 0.0 : tz / d->crho;
 }
 
-// Half-width in longitude of the part of ring i that can lie within the
-// disk: the same bound as in ring_cap_ranges.  Returns 0 when the ring's
-// latitude extent misses the disk, 2 when the whole ring may be inside
-// (*dphi untouched), else 1 with the half-width in *dphi.
-CG_HD int ring_disk_halfwidth(int64_t nside, int64_t i, const DiskPrep& d, double* dphi) {
-  const double eps = 1e-12;
-  const double zl = ring_z(nside, i + 1) - eps;
-  const double zh = ring_z(nside, i - 1) + eps;
+// Half-width in longitude of the part of a latitude band [zl, zh] that can
+// lie within the disk: the same bound as in ring_cap_ranges.  Returns 0 when
+// the band misses the disk, 2 when the whole band may be inside (*dphi
+// untouched), else 1 with the half-width in *dphi.
+CG_HD int band_disk_halfwidth(double zl, double zh, const DiskPrep& d, double* dphi) {
   const double a = zl > d.zmin ? zl : d.zmin;
   const double b = zh < d.zmax ? zh : d.zmax;
   if (a > b) return 0;
@@ -262,6 +259,19 @@ CG_HD int ring_disk_halfwidth(int64_t nside, int64_t i, const DiskPrep& d, doubl
   return 1;
 }
 
+// Latitude band holding every point whose pixel lies in ring i, widened by
+// 1e-12 for rounding.
+CG_HD void ring_band(int64_t nside, int64_t i, double* zl, double* zh) {
+  *zl = ring_z(nside, i + 1) - 1e-12;
+  *zh = ring_z(nside, i - 1) + 1e-12;
+}
+
+CG_HD int ring_disk_halfwidth(int64_t nside, int64_t i, const DiskPrep& d, double* dphi) {
+  double zl, zh;
+  ring_band(nside, i, &zl, &zh);
+  return band_disk_halfwidth(zl, zh, d, dphi);
+}
+
 // Longitude of a point relative to a reference longitude, in (-pi, pi].
 CG_HD double rel_lon(double phi, double ref) {
   double r = phi - ref;
@@ -273,8 +283,8 @@ CG_HD double rel_lon(double phi, double ref) {
 // Union over a set of disks of their longitude windows on ring i, as one
 // window [*plo, *phi] (absolute longitudes, possibly outside [0, 2 pi)) or
 // the whole ring (*full).  rel[k] is the centre longitude of disk k relative
-// to ref.  Returns 0 when no disk meets the ring.  The kernels form the same
-// union with one disk per lane and wavefront reductions.
+// to ref.  Returns 0 when no disk meets the ring.  The tile kernel forms the
+// same union with one ring per lane.
 CG_HD int ring_union_window(int64_t nside, int64_t i, const DiskPrep* d, const double* rel,
                             int n, double ref, double* plo, double* phi, int* full) {
   double lo = 1e300, hi = -1e300;
