@@ -195,6 +195,89 @@ cg_status cg_profile_enable(cg_gridder* g, int32_t enable);
 cg_status cg_profile_read(cg_gridder* g, int64_t* launches, double* total_ms);
 
 void cg_destroy(cg_gridder* g);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent gridding jobs of uneven size (sample counts, grids,
+ * channel counts, circular or elliptical kernels) evaluated in one pass:
+ * one concatenated HEALPix index + sort + ring-offset + lookup pass over the
+ * samples of all jobs, and one persistent matrix-core launch over a queue of
+ * (job, tile, channel range) items ordered by estimated cost, largest first.
+ * Each job computes exactly what cg_grid_datacube computes for its gridder
+ * (Eq. 1-3, the same exact support test and the same precision mode).  The
+ * paper grids one data set per call (Sect. 3.5); batching is this library's
+ * addition for throughput. */
+typedef struct cg_batch cg_batch;
+
+/* Inputs and outputs of one job (all device pointers; see cg_grid_datacube
+ * for layouts).  data rows are of the batch's dtype; weights_out may be NULL. */
+typedef struct cg_batch_job {
+  const double* lon_deg;   /* [nsamples] */
+  const double* lat_deg;   /* [nsamples] */
+  const void* data;        /* [nsamples][ld_data] */
+  int64_t nsamples;        /* >= 0 */
+  int64_t ld_data;         /* >= the job's nchan */
+  float* cube_out;         /* [nchan][naxis2][naxis1] or [nchan][ntarget] */
+  float* weights_out;      /* [naxis2][naxis1] or [ntarget], or NULL */
+} cg_batch_job;
+
+/* Create a batch over njobs (1..256) gridders, borrowed: they must outlive
+ * the batch, must not be used for other calls while it runs, and must not be
+ * reconfigured (cg_set_kernel, cg_set_nside) while it exists (a pass or
+ * replay that finds a changed gridder returns CG_E_STATE).  Every gridder
+ * needs set_kernel and the same matrix-core precision (CG_PREC_BF16 or
+ * CG_PREC_FP16, set with cg_set_precision); dtype is the data type of every
+ * job's rows.  Waits for the device once (tile tables).  Errors:
+ * CG_E_INVALID, CG_E_STATE (a gridder without kernel), CG_E_UNSUPPORTED
+ * (CG_PREC_FP32 or mixed precisions or devices), CG_E_OOM, CG_E_DEVICE. */
+cg_status cg_batch_create(cg_batch** out, cg_gridder* const* jobs, int32_t njobs, int32_t dtype);
+
+/* One pass over all jobs: in[njobs] (host array of device pointers).  Writes
+ * every job's cube and weights.  Synchronises `stream` once to size the
+ * candidate lists.  Invalid sample coordinates are skipped and reported by
+ * cg_batch_sync.  Errors: CG_E_INVALID, CG_E_OOM, CG_E_DEVICE. */
+cg_status cg_batch_grid(cg_batch* b, const cg_batch_job* in, void* stream);
+
+/* Autotuner: runs one cg_batch_grid on `in`, then times each configuration
+ * of the persistent launch (channels per item: 256 or 512 matrix rows per
+ * workgroup, items of full or half width, one or all resident workgroups per
+ * compute unit) `reps` times on the same lookup and keeps the fastest for
+ * later calls.  The outputs hold a valid result afterwards.  Waits for the
+ * device.  Errors as cg_batch_grid. */
+cg_status cg_batch_tune(cg_batch* b, const cg_batch_job* in, int32_t reps, void* stream);
+
+/* Record one cg_batch_grid step on `in` as a HIP graph (after running it
+ * once eagerly to size every buffer), for replay by cg_batch_replay without
+ * host synchronisation.  The graph keeps the device pointers of `in` and the
+ * candidate capacity of the eager run; a replay whose samples need more
+ * candidates writes nothing and is reported by cg_batch_sync (capture
+ * again).  A later cg_batch_grid that must enlarge a buffer, or
+ * cg_batch_tune, drops the graph.  Waits for the device.  Errors as
+ * cg_batch_grid. */
+cg_status cg_batch_capture(cg_batch* b, const cg_batch_job* in, void* stream);
+
+/* Launch the captured graph on `stream`.  Errors: CG_E_STATE (no graph),
+ * CG_E_DEVICE. */
+cg_status cg_batch_replay(cg_batch* b, void* stream);
+
+/* Wait for `stream`; CG_E_INPUT if an invalid sample coordinate was seen,
+ * CG_E_STATE if a replay exceeded the captured candidate capacity (both
+ * flags are then cleared), CG_E_DEVICE on a HIP failure, else CG_OK. */
+cg_status cg_batch_sync(cg_batch* b, void* stream);
+
+/* Batch queries (host): what = 0 njobs, 1 samples of the last pass,
+ * 2 tiles, 3 work items, 4 candidates of the last eager pass, 5 matrix rows
+ * per workgroup (256 or 512), 6 half-width items (0/1), 7 workgroups per
+ * compute unit, 8 graph captured (0/1). */
+cg_status cg_batch_query(const cg_batch* b, int32_t what, int64_t* value);
+
+/* Measurement as cg_profile_enable / cg_profile_read: events bracket the
+ * persistent contraction launch of each eager pass, and the whole step of
+ * each replay. */
+cg_status cg_batch_profile_enable(cg_batch* b, int32_t enable);
+cg_status cg_batch_profile_read(cg_batch* b, int64_t* launches, double* total_ms);
+
+void cg_batch_destroy(cg_batch* b);
+
 const char* cg_last_error(void);
 const char* cg_version(void);
 

@@ -34,6 +34,12 @@ class CgWcs(C.Structure):
                 ("cdelt1", C.c_double), ("cdelt2", C.c_double)]
 
 
+class CgBatchJob(C.Structure):
+    _fields_ = [("lon_deg", C.c_void_p), ("lat_deg", C.c_void_p), ("data", C.c_void_p),
+                ("nsamples", C.c_int64), ("ld_data", C.c_int64),
+                ("cube_out", C.c_void_p), ("weights_out", C.c_void_p)]
+
+
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 _P = C.POINTER
 
@@ -54,6 +60,16 @@ SIGNATURES = {
     "cg_profile_enable": (_i32, [_vp, _i32]),
     "cg_profile_read": (_i32, [_vp, _P(_i64), _P(_d)]),
     "cg_destroy": (None, [_vp]),
+    "cg_batch_create": (_i32, [_P(_vp), _P(_vp), _i32, _i32]),
+    "cg_batch_grid": (_i32, [_vp, _P(CgBatchJob), _vp]),
+    "cg_batch_tune": (_i32, [_vp, _P(CgBatchJob), _i32, _vp]),
+    "cg_batch_capture": (_i32, [_vp, _P(CgBatchJob), _vp]),
+    "cg_batch_replay": (_i32, [_vp, _vp]),
+    "cg_batch_sync": (_i32, [_vp, _vp]),
+    "cg_batch_query": (_i32, [_vp, _i32, _P(_i64)]),
+    "cg_batch_profile_enable": (_i32, [_vp, _i32]),
+    "cg_batch_profile_read": (_i32, [_vp, _P(_i64), _P(_d)]),
+    "cg_batch_destroy": (None, [_vp]),
     "cg_last_error": (C.c_char_p, []),
     "cg_version": (C.c_char_p, []),
     "cg_hpx_ang2pix_ring": (_i32, [_i64, _i64, _vp, _vp, _vp]),
@@ -311,6 +327,101 @@ class SlGrid(_Gridder):
         self._h = h
         self.out_shape = (int(lon.shape[0]),)
         self.device = self.query(6)
+
+
+class Batch:
+    """Many gridding jobs evaluated in one lookup pass and one persistent
+    contraction launch (cg_batch_* of the C ABI).  ``gridders`` are WcsGrid /
+    SlGrid objects with their kernel and matrix-core precision set; every
+    job's data has the same dtype."""
+
+    def __init__(self, gridders, dtype):
+        torch = _torch()
+        codes = {torch.float64: F64, torch.float32: F32, torch.float16: F16,
+                 torch.bfloat16: BF16}
+        if dtype not in codes:
+            raise TypeError(f"unsupported data dtype {dtype}")
+        self.gridders = list(gridders)
+        self.dtype = dtype
+        arr = (C.c_void_p * len(self.gridders))(*[g._handle().value for g in self.gridders])
+        h = C.c_void_p()
+        check(lib().cg_batch_create(C.byref(h), arr, len(self.gridders), codes[dtype]))
+        self._h = h
+        self._keep = None
+
+    def __del__(self):
+        try:
+            if self._h is not None and _LIB is not None:
+                _LIB.cg_batch_destroy(self._h)
+        except Exception:
+            pass
+        self._h = None
+
+    def close(self):
+        if self._h is not None:
+            lib().cg_batch_destroy(self._h)
+            self._h = None
+
+    def _jobs(self, inputs, outputs):
+        """inputs: [(lon, lat, data)], outputs: [(cube, weights or None)]."""
+        torch = _torch()
+        if len(inputs) != len(self.gridders) or len(outputs) != len(self.gridders):
+            raise ValueError("one (lon, lat, data) and one (cube, weights) per job")
+        arr = (CgBatchJob * len(self.gridders))()
+        keep = []
+        for j, (g, (lon, lat, data), (cube, wts)) in enumerate(zip(self.gridders, inputs, outputs)):
+            if data.dtype != self.dtype:
+                raise TypeError(f"job {j}: data dtype {data.dtype} != batch dtype {self.dtype}")
+            n = int(lon.shape[0])
+            sig = _data2d(data, g.nchan)
+            pl, pb = g._coords(lon, lat)
+            arr[j].lon_deg = pl.value
+            arr[j].lat_deg = pb.value
+            arr[j].data = sig.data_ptr() if n else None
+            arr[j].nsamples = n
+            arr[j].ld_data = int(sig.stride(0)) if n else g.nchan
+            arr[j].cube_out = _dev_ptr(cube, torch.float32, "cube").value
+            arr[j].weights_out = (_dev_ptr(wts, torch.float32, "weights").value
+                                  if wts is not None else None)
+            keep.append((lon, lat, sig, cube, wts))
+        return arr, keep
+
+    def outputs(self):
+        return [(g._empty_out(g.nchan), g._empty_out(0)) for g in self.gridders]
+
+    def grid(self, inputs, outputs, stream=None):
+        arr, keep = self._jobs(inputs, outputs)
+        check(lib().cg_batch_grid(self._h, arr, _stream(stream)))
+        self._keep = keep
+
+    def tune(self, inputs, outputs, reps=3, stream=None):
+        arr, keep = self._jobs(inputs, outputs)
+        check(lib().cg_batch_tune(self._h, arr, int(reps), _stream(stream)))
+        self._keep = keep
+
+    def capture(self, inputs, outputs, stream=None):
+        arr, keep = self._jobs(inputs, outputs)
+        check(lib().cg_batch_capture(self._h, arr, _stream(stream)))
+        self._keep = keep   # the graph holds these pointers
+
+    def replay(self, stream=None):
+        check(lib().cg_batch_replay(self._h, _stream(stream)))
+
+    def sync(self, stream=None):
+        check(lib().cg_batch_sync(self._h, _stream(stream)))
+
+    def query(self, what):
+        v = C.c_int64()
+        check(lib().cg_batch_query(self._h, int(what), C.byref(v)))
+        return v.value
+
+    def profile(self, enable=True):
+        check(lib().cg_batch_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        n, ms = C.c_int64(), C.c_double()
+        check(lib().cg_batch_profile_read(self._h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
 
 # ------------------------------------------------------- host-side helpers

@@ -1,0 +1,170 @@
+// Persistent matrix-core contraction for a batch of gridding jobs.
+//
+// Every (job, tile, channel range) of the batch is one work item; the items
+// sit in one queue ordered by estimated cost, largest first (longest
+// processing time first), and a grid sized to the resident capacity of the
+// chip takes them one at a time from an atomic counter, so jobs of very
+// different sizes share one launch without a tail of idle compute units.
+// Each item runs the same tile contraction as the per-grid kernel, with the
+// kernel type (circular or elliptical) taken from the job at run time, and
+// writes the normalised cube and weights of its job directly.
+#include "cg_mfma_tile.hpp"
+
+namespace cg {
+
+__device__ __noinline__ double chord2_to_d2_exact(double c2) {
+  const double d = 2.0 * asin(0.5 * sqrt(c2));
+  return d * d;
+}
+
+constexpr int kBatchWaves = 8;
+
+template <int BPW, int MODE, typename T>
+__global__ void __launch_bounds__(kBatchWaves * 64) k_batch_mfma(
+    const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, int64_t nitems,
+    int* counter, const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ cand,
+    const uint32_t* __restrict__ crow, const double* __restrict__ cxyz, int64_t ncap,
+    const T* __restrict__ zrow, const int* __restrict__ ovf) {
+  __shared__ int s_item;
+  if (*ovf) return;   // candidate buffers too small: nothing is written
+  for (;;) {
+    __syncthreads();  // the previous item is done with LDS
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= nitems) break;
+    const BatchItem item = items[it];
+    const BatchJob& jb = jobs[item.job];
+    TileView tv;
+    tv.txyz = jb.txyz;
+    tv.tll = jb.tll;
+    tv.cand_off = cand_off + jb.toff;
+    tv.cand = cand;
+    tv.crow = crow;
+    tv.cxyz = cxyz;
+    tv.nslots = jb.nslots;
+    tv.ncap = ncap;
+    tv.ntiles = jb.ntiles;
+    OutView ov;
+    ov.S = nullptr;
+    ov.W = nullptr;
+    ov.Wn = nullptr;
+    ov.cube = jb.cube;
+    ov.wout = jb.wout;
+    ov.slot_target = jb.slot_target;
+    ov.ntarget = jb.ntarget;
+    ov.mode = ACC_FINAL;
+    mfma_tile<kBatchWaves, BPW, 2, MODE, false, T>(tv, jb.kp, (const T*)jb.data, zrow, jb.ld,
+                                                   jb.nchan, ov, item.tile, item.c0, item.cend);
+  }
+}
+
+template <int BPW, int MODE, typename T>
+static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
+                            int* counter, const uint64_t* cand_off, const uint32_t* cand,
+                            const uint32_t* crow, const double* cxyz, int64_t ncap,
+                            const void* zrow, int blocks_per_cu, const int* ovf, hipStream_t st) {
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  int occ = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_mfma<BPW, MODE, T>,
+                                                   kBatchWaves * 64, 0);
+  if (e != hipSuccess) return e;
+  int per = blocks_per_cu > 0 && blocks_per_cu < occ ? blocks_per_cu : occ;
+  if (per < 1) per = 1;
+  int64_t grid = (int64_t)ncu * per;
+  if (grid > nitems) grid = nitems;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((k_batch_mfma<BPW, MODE, T>), dim3((unsigned)grid), dim3(kBatchWaves * 64), 0,
+                     st, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
+                     (const T*)zrow, ovf);
+  return hipGetLastError();
+}
+
+template <int MODE, typename T>
+static hipError_t launch_bp(int bpw, const BatchJob* jobs, const BatchItem* items, int64_t nitems,
+                            int* counter, const uint64_t* cand_off, const uint32_t* cand,
+                            const uint32_t* crow, const double* cxyz, int64_t ncap,
+                            const void* zrow, int blocks_per_cu, const int* ovf, hipStream_t st) {
+  switch (bpw) {
+    case 1:
+      return launch_bt<1, MODE, T>(jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
+                                   zrow, blocks_per_cu, ovf, st);
+    case 2:
+      return launch_bt<2, MODE, T>(jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
+                                   zrow, blocks_per_cu, ovf, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int MODE>
+static hipError_t launch_bm(int dtype, int bpw, const BatchJob* jobs, const BatchItem* items,
+                            int64_t nitems, int* counter, const uint64_t* cand_off,
+                            const uint32_t* cand, const uint32_t* crow, const double* cxyz,
+                            int64_t ncap, const void* zrow, int blocks_per_cu, const int* ovf,
+                            hipStream_t st) {
+  switch (dtype) {
+    case 0:
+      return launch_bp<MODE, double>(bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
+                                     ncap, zrow, blocks_per_cu, ovf, st);
+    case 1:
+      return launch_bp<MODE, float>(bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
+                                    ncap, zrow, blocks_per_cu, ovf, st);
+    case 2:
+      return launch_bp<MODE, _Float16>(bpw, jobs, items, nitems, counter, cand_off, cand, crow,
+                                       cxyz, ncap, zrow, blocks_per_cu, ovf, st);
+    default:
+      return launch_bp<MODE, uint16_t>(bpw, jobs, items, nitems, counter, cand_off, cand, crow,
+                                       cxyz, ncap, zrow, blocks_per_cu, ovf, st);
+  }
+}
+
+hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
+                             int* counter, const uint64_t* cand_off, const uint32_t* cand,
+                             const uint32_t* crow, const double* cxyz, int64_t ncap,
+                             const void* zrow, int dtype, int prec, int bpw, int blocks_per_cu,
+                             const int* ovf, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (prec == 2)
+    return launch_bm<1>(dtype, bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
+                        zrow, blocks_per_cu, ovf, st);
+  return launch_bm<0>(dtype, bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
+                      zrow, blocks_per_cu, ovf, st);
+}
+
+template <int BPW, int MODE, typename T>
+static int occ_of() {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_mfma<BPW, MODE, T>,
+                                                   kBatchWaves * 64, 0) != hipSuccess)
+    return 0;
+  return occ;
+}
+
+template <int MODE, typename T>
+static int occ_b(int bpw) {
+  switch (bpw) {
+    case 1: return occ_of<1, MODE, T>();
+    case 2: return occ_of<2, MODE, T>();
+    default: return 0;
+  }
+}
+
+template <int MODE>
+static int occ_m(int dtype, int bpw) {
+  switch (dtype) {
+    case 0: return occ_b<MODE, double>(bpw);
+    case 1: return occ_b<MODE, float>(bpw);
+    case 2: return occ_b<MODE, _Float16>(bpw);
+    default: return occ_b<MODE, uint16_t>(bpw);
+  }
+}
+
+int batch_max_blocks_per_cu(int dtype, int prec, int bpw) {
+  return prec == 2 ? occ_m<1>(dtype, bpw) : occ_m<0>(dtype, bpw);
+}
+
+}  // namespace cg

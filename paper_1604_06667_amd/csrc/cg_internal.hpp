@@ -163,6 +163,83 @@ hipError_t launch_gather_mfma(const TileView& tv, const KernelParams& kp, const 
                               const void* zrow, int dtype, int64_t ld, int64_t nchan, int prec,
                               const OutView& ov, hipStream_t st);
 bool mfma_available();
+
+// ---------------------------------------------------------------- batches
+// One job of a batch: its samples, its gridder's targets and tiles, where
+// its pieces sit in the batch's concatenated arrays, and its outputs.
+struct BatchJob {
+  const double* lon;           // [n] sample longitudes (deg)
+  const double* lat;           // [n] sample latitudes (deg)
+  const void* data;            // [n][ld] sample rows
+  int64_t n, noff;             // samples; offset in the concatenated sample order
+  int64_t ld, nchan, nside;
+  int64_t ro_off;              // offset of the ring offsets [4 nside + 1]
+  int64_t toff, ntiles, nslots;  // first global tile; tiles; target slots
+  int64_t rbase;               // offset (in ranges) of the job's range slots
+  int64_t ntarget;
+  const double* txyz;
+  const double* tll;
+  const double* caps;
+  const int32_t* ring_first;
+  const uint64_t* range_off;   // [ntiles + 1] job-local range-slot offsets
+  const int32_t* slot_target;
+  float* cube;                 // [nchan][ntarget] normalised output
+  float* wout;                 // [ntarget] weight map (may be null)
+  KernelParams kp;
+  double rho;                  // support radius + margin (rad)
+};
+// One work item of the persistent contraction: a tile of a job and a channel
+// range [c0, cend).
+struct BatchItem {
+  int32_t job, tile, c0, cend;
+};
+
+// Largest j in [0, n) with off[j] <= x (off ascending, off[0] = 0): the job
+// whose range [off[j], off[j + 1]) holds x (empty jobs are skipped).
+__device__ __forceinline__ int job_of(const int64_t* __restrict__ off, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+hipError_t launch_batch_prep(const BatchJob* jobs, const int64_t* noff, int njobs, int64_t ntot,
+                             uint32_t* keys, uint32_t* vals, int* flag, hipStream_t st);
+// Stable LSD sort by the low `bits` of the keys, then one more stable pass by
+// the job of each value (values are positions in the concatenated order), so
+// the result is job-major and sorted by key within each job.
+hipError_t radix_sort_jobs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                           uint32_t* hist, int64_t n, int bits, const int64_t* noff, int njobs,
+                           bool* result_in_tmp, hipStream_t st);
+hipError_t launch_batch_ring_offsets(const BatchJob* jobs, const int64_t* rooff, int njobs,
+                                     int64_t nentries, const uint32_t* keys, uint32_t* ring_off,
+                                     hipStream_t st);
+hipError_t launch_batch_permute(const BatchJob* jobs, const int64_t* noff, int njobs, int64_t ntot,
+                                const uint32_t* vals, const uint32_t* ring_off, double* sx,
+                                hipStream_t st);
+hipError_t launch_batch_tile_ranges(const BatchJob* jobs, const int64_t* toff, int njobs,
+                                    int64_t ntiles, const uint32_t* keys, const uint32_t* ring_off,
+                                    uint32_t* ranges, uint32_t* nranges, uint64_t* ncand,
+                                    hipStream_t st);
+// ovf[0] = ovf[1] = 1 if the candidates exceed cap (ovf[1] is sticky)
+hipError_t launch_batch_guard(const uint64_t* cand_off, int64_t ntiles, int64_t cap, int* ovf,
+                              hipStream_t st);
+hipError_t launch_batch_expand(const BatchJob* jobs, const int64_t* toff, int njobs, int64_t ntiles,
+                               const uint32_t* ranges, const uint32_t* nranges,
+                               const uint64_t* cand_off, const uint32_t* vals, const double* sx,
+                               int64_t nsorted, uint32_t* cand, uint32_t* crow, double* cxyz,
+                               int64_t ncap, const int* ovf, hipStream_t st);
+// Persistent contraction over a queue of items (bpw 1 or 2: at most 256 * bpw
+// channels per item); counter must be zero at launch.
+hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
+                             int* counter, const uint64_t* cand_off, const uint32_t* cand,
+                             const uint32_t* crow, const double* cxyz, int64_t ncap,
+                             const void* zrow, int dtype, int prec, int bpw, int blocks_per_cu,
+                             const int* ovf, hipStream_t st);
+int batch_max_blocks_per_cu(int dtype, int prec, int bpw);
 hipError_t launch_stats(const TileView& tv, const KernelParams& kp, const int32_t* slot_target,
                         int32_t* counts, uint64_t* hashes, hipStream_t st);
 hipError_t launch_normalize(const float* S, const double* W, const double* Wn,

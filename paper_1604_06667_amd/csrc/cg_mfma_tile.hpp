@@ -1,0 +1,391 @@
+// Matrix-core contraction of one tile of 64 targets over a channel range:
+// the device code shared by the per-grid kernel and the persistent batch
+// kernel.  Description of the method and data flow: cg_mfma.hip.
+#pragma once
+#include <type_traits>
+
+#include "cg_internal.hpp"
+
+namespace cg {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+template <bool F16>
+__device__ __forceinline__ uint16_t to_bits(float x) {
+  if constexpr (F16) {
+    const _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(uint16_t, h);
+  } else {
+    const __bf16 h = (__bf16)x;
+    return __builtin_bit_cast(uint16_t, h);
+  }
+}
+
+template <bool F16>
+__device__ __forceinline__ float from_bits(uint16_t b) {
+  if constexpr (F16) return (float)__builtin_bit_cast(_Float16, b);
+  else return __uint_as_float((uint32_t)b << 16);
+}
+
+// Two floats -> two packed 16-bit values (round to nearest even), element a
+// in the low half.
+template <bool F16>
+__device__ __forceinline__ uint32_t cvt_pk(float a, float b) {
+  if constexpr (F16) {
+    return (uint32_t)to_bits<true>(a) | ((uint32_t)to_bits<true>(b) << 16);
+  } else {
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+  }
+}
+
+// The two packed values as floats.
+template <bool F16>
+__device__ __forceinline__ float unpk_lo(uint32_t p) {
+  if constexpr (F16) return from_bits<true>((uint16_t)(p & 0xffffu));
+  else return __uint_as_float(p << 16);
+}
+template <bool F16>
+__device__ __forceinline__ float unpk_hi(uint32_t p) {
+  if constexpr (F16) return from_bits<true>((uint16_t)(p >> 16));
+  else return __uint_as_float(p & 0xffff0000u);
+}
+
+template <typename T>
+__device__ __forceinline__ float in_f32(const T* p);
+template <>
+__device__ __forceinline__ float in_f32<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float in_f32<double>(const double* p) { return (float)*p; }
+template <>
+__device__ __forceinline__ float in_f32<uint16_t>(const uint16_t* p) {
+  return __uint_as_float(((uint32_t)*p) << 16);
+}
+template <>
+__device__ __forceinline__ float in_f32<_Float16>(const _Float16* p) { return (float)*p; }
+
+// 4 consecutive channels of one row as floats (zeros past nvalid).
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ p, int nvalid, bool vec_ok, float* o) {
+  if (vec_ok && nvalid >= 4) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+      return;
+    } else if constexpr (sizeof(T) == 2) {
+      const uint2 v = *reinterpret_cast<const uint2*>(p);
+      const uint16_t h[4] = {(uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16),
+                             (uint16_t)(v.y & 0xffff), (uint16_t)(v.y >> 16)};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = in_f32<T>(reinterpret_cast<const T*>(&h[i]));
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o[i] = (i < nvalid) ? in_f32<T>(p + i) : 0.0f;
+}
+
+// MODE 0: BF16 with hi/lo split of data and weights, three products per
+//         block (hi*hi + lo*hi + hi*lo);
+// MODE 1: FP16, one product per block.
+//
+// Work of one workgroup: one tile (64 targets) x CP channels.  Wavefront w
+// owns channel blocks [w*BPW, (w+1)*BPW) of 32 channels; lane l holds
+// channel l%32 of a block and the 8 samples 8*(l/32) .. +7 of a 16-sample
+// chunk, i.e. exactly its MFMA A operand, so the data never passes through
+// LDS: each lane loads its 8 values straight from the sample rows (one
+// 128-byte segment per row and half-wave) and converts them in registers.
+// Only the 64 x 16 weight block is shared through LDS (double buffered).
+// Software pipeline, one barrier per chunk: while chunk i is on the matrix
+// cores, the same wavefront computes the weight block of chunk i+1 and
+// reloads its data registers with chunk i+1; candidate records run two
+// chunks ahead through a three-deep LDS ring.  Past-the-end candidates point
+// at a row of zeros, so the loads need no bounds selects.  FULL: the channel
+// count is a multiple of CP (no channel bounds checks).
+template <int NW, int BPW, int KT, int MODE, bool FULL, typename T>
+__device__ __forceinline__ void mfma_tile(const TileView& tv, const KernelParams& kp,
+                                          const T* __restrict__ data, const T* __restrict__ zrow,
+                                          int64_t ld, int64_t nchan, const OutView& ov,
+                                          int64_t tile, int64_t c0, int64_t cend) {
+  constexpr bool F16 = MODE == 1;
+  constexpr bool SPLIT = MODE == 0;
+  constexpr bool BF16IN = std::is_same<T, uint16_t>::value;
+  constexpr int NS = SPLIT ? 2 : 1;              // hi (+ lo) parts
+  constexpr int MK = 16;                         // candidate samples per chunk
+  constexpr int KP = MK + 8;                     // padded LDS row of the weight block
+  constexpr int CP = NW * BPW * 32;              // channels per pass
+  using opv_t = typename std::conditional<F16, f16x8_t, bf16x8_t>::type;
+  __shared__ __attribute__((aligned(16))) uint16_t s_wt[2][NS][kTile * KP];  // [buf][part][target][sample]
+  __shared__ double s_c[3][MK][3];
+  __shared__ int64_t s_row[3][MK];   // element offset of each candidate's row from data
+  __shared__ double s_red[2][NW][kTile];
+  __shared__ double s_wfin[2][kTile];
+  __shared__ double s_tg[kTile][KT == 0 ? 3 : 9];   // target xyz (+ major, minor axis)
+
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t ns = tv.nslots;
+  const int64_t cap = tv.ncap;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  const int cl = lane & 31;      // channel within a 32-channel block / target within a 32-target block
+  const int kh = lane >> 5;      // which 8 samples of the chunk this lane holds
+  const int64_t cbase = c0 + wv * BPW * 32 + cl;   // this lane's channel in block 0
+  // KT 2: kernel type chosen at run time (batched jobs of both types)
+  const bool ell = KT == 1 || (KT == 2 && kp.type == 1);
+  bool bvalid[BPW];    // this lane's channel of block b exists
+  bool bany[BPW];      // block b has any channel (uniform over the wavefront)
+#pragma unroll
+  for (int b = 0; b < BPW; ++b) {
+    bvalid[b] = FULL || (cbase + 32 * b < cend);
+    bany[b] = FULL || (c0 + (wv * BPW + b) * 32 < cend);
+  }
+
+  if (t < kTile) {
+    const int64_t wslot = tile * kTile + t;
+    const double x = tv.txyz[wslot];
+    s_tg[t][0] = x;
+    s_tg[t][1] = tv.txyz[ns + wslot];
+    s_tg[t][2] = tv.txyz[2 * ns + wslot];
+    if constexpr (KT != 0) {
+      double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+      if (ell && isfinite(x)) {
+        double sa, ca, sd, cd;
+        sincos(tv.tll[wslot], &sa, &ca);
+        sincos(tv.tll[ns + wslot], &sd, &cd);
+        const double ex = -sa, ey = ca, nx = -sd * ca, ny = -sd * sa, nz = cd;
+        a[0] = kp.cospa * nx + kp.sinpa * ex;
+        a[1] = kp.cospa * ny + kp.sinpa * ey;
+        a[2] = kp.cospa * nz;
+        b[0] = kp.cospa * ex - kp.sinpa * nx;
+        b[1] = kp.cospa * ey - kp.sinpa * ny;
+        b[2] = -kp.sinpa * nz;
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        s_tg[t][3 + q] = a[q];
+        s_tg[t][6 + q] = b[q];
+      }
+    }
+  }
+  // this thread's target in the weight block and its candidates kg, kg + NW, ...
+  const int nw = t & 63;
+  const int kg = t >> 6;
+  double wsum = 0.0, wsum_r = 0.0;
+
+  f32x16_t acc[BPW][2];
+#pragma unroll
+  for (int b = 0; b < BPW; ++b)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[b][nb][j] = 0.0f;
+
+  const uint64_t cb0 = tv.cand_off[tile], cb1 = tv.cand_off[tile + 1];
+  const int64_t nchunks = (int64_t)((cb1 - cb0 + MK - 1) / MK);
+
+  // candidate record of chunk ch for thread t < MK (NaN / zero row past the end)
+  const int64_t zoff = (int64_t)(zrow - data) - c0;   // offset that lands on the zero row
+  double rx = nan, ry = nan, rz = nan;
+  int64_t rrow = zoff;
+  auto load_rec = [&](int64_t ch) {
+    const uint64_t q = cb0 + (uint64_t)ch * MK + t;
+    if (ch < nchunks && q < cb1) {
+      rx = tv.cxyz[q];
+      ry = tv.cxyz[cap + q];
+      rz = tv.cxyz[2 * cap + q];
+      rrow = (int64_t)tv.crow[q] * ld;
+    } else {
+      rx = ry = rz = nan;
+      rrow = zoff;   // + channel offsets below stays inside the zero row
+    }
+  };
+  auto put_rec = [&](int buf) {
+    s_c[buf][t][0] = rx;
+    s_c[buf][t][1] = ry;
+    s_c[buf][t][2] = rz;
+    s_row[buf][t] = rrow;
+  };
+  // weight of candidate k of the chunk in record buffer rb -> weight buffer wb
+  auto weight = [&](int rb, int wb, int k) {
+    const double dx = s_c[rb][k][0] - s_tg[nw][0];
+    const double dy = s_c[rb][k][1] - s_tg[nw][1];
+    const double dz = s_c[rb][k][2] - s_tg[nw][2];
+    const double c2 = dx * dx + dy * dy + dz * dz;
+    float w = 0.0f;
+    if (c2 <= kp.cs2) {
+      if constexpr (KT == 0) {
+        w = exp2_neg(chord2_to_d2(c2) * kp.k1);
+      } else {
+        if (ell)
+          w = pair_weight(kp, c2, dx, dy, dz, s_tg[nw][3], s_tg[nw][4], s_tg[nw][5],
+                          s_tg[nw][6], s_tg[nw][7], s_tg[nw][8]);
+        else
+          w = exp2_neg(chord2_to_d2(c2) * kp.k1);
+      }
+    }
+    const uint16_t whi = to_bits<F16>(w);
+    float wr = from_bits<F16>(whi);
+    s_wt[wb][0][nw * KP + k] = whi;
+    if constexpr (SPLIT) {
+      const uint16_t wlo = to_bits<F16>(w - wr);
+      s_wt[wb][NS - 1][nw * KP + k] = wlo;
+      wr += from_bits<F16>(wlo);
+    }
+    wsum += (double)w;
+    wsum_r += (double)wr;
+  };
+  // this lane's A-operand values (raw input) of one chunk
+  float raw[BPW][8];
+  auto load_block = [&](int rb, int b) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const T* p = data + (s_row[rb][8 * kh + i] + cbase + 32 * b);
+      raw[b][i] = bvalid[b] ? in_f32<T>(p) : 0.0f;
+    }
+  };
+
+  // prologue: records of chunks 0, 1 in LDS, of chunk 2 in registers; the
+  // weights and data of chunk 0
+  if (t < MK) {
+    load_rec(0);
+    put_rec(0);
+    load_rec(1);
+    put_rec(1);
+    load_rec(2);
+  }
+  __syncthreads();
+  if (nchunks > 0) {
+#pragma unroll
+    for (int k = kg; k < MK; k += NW) weight(0, 0, k);
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) load_block(0, b);
+  }
+
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int wc = (int)(ch & 1);                 // weight buffer of chunk ch
+    const int r1 = (int)((ch + 1) % 3);           // record buffer of chunk ch+1
+    __syncthreads();
+    // records: publish chunk ch+2, fetch chunk ch+3
+    if (t < MK) {
+      put_rec((int)((ch + 2) % 3));
+      load_rec(ch + 3);
+    }
+    const int kofs = 8 * kh;
+    opv_t bop[NS][2];
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        bop[sp][nb] = *reinterpret_cast<const opv_t*>(&s_wt[wc][sp][(nb * 32 + cl) * KP + kofs]);
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      // this lane's data of chunk ch -> MFMA operands (hi, lo); refill with chunk ch+1
+      opv_t aop[NS];
+      {
+        uint32_t hp[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hp[q] = cvt_pk<F16>(raw[b][2 * q], raw[b][2 * q + 1]);
+        aop[0] = __builtin_bit_cast(opv_t, hp);
+        if constexpr (SPLIT && !BF16IN) {
+          uint32_t lp[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            lp[q] = cvt_pk<F16>(raw[b][2 * q] - unpk_lo<F16>(hp[q]),
+                                raw[b][2 * q + 1] - unpk_hi<F16>(hp[q]));
+          aop[NS - 1] = __builtin_bit_cast(opv_t, lp);
+        }
+      }
+      load_block(r1, b);   // past the last chunk this reads the zero row
+      // independent accumulators back to back; the residual products last
+      if (!bany[b]) {
+        // no channel of this block: nothing to accumulate
+      } else if constexpr (F16) {
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
+        if constexpr (SPLIT) {
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[1][nb], acc[b][nb], 0, 0, 0);
+          if constexpr (!BF16IN) {
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+              acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[1], bop[0][nb], acc[b][nb], 0, 0, 0);
+          }
+        }
+      }
+      // weight block of chunk ch+1 (all zero past the last chunk), spread over
+      // the channel blocks
+#pragma unroll
+      for (int k = kg + b * NW; k < MK; k += BPW * NW) weight(r1, wc ^ 1, k);
+    }
+  }
+  __syncthreads();
+
+  // weight sums of each target (8 partial sums per target)
+  s_red[0][kg][nw] = wsum;
+  s_red[1][kg][nw] = wsum_r;
+  __syncthreads();
+  if (t < kTile) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      a += s_red[0][q][t];
+      b += s_red[1][q][t];
+    }
+    s_wfin[0][t] = a;
+    s_wfin[1][t] = b;
+  }
+  __syncthreads();
+
+  // outputs: lane holds target n = nb*32 + lane%32, channels m = 8(j/4) + 4(lane/32) + j%4
+  const bool fin = ov.mode == ACC_FINAL;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int n = nb * 32 + (lane & 31);
+    const int64_t slot = tile * kTile + n;
+    const double wr = s_wfin[1][n];
+    const int32_t tg = fin ? ov.slot_target[slot] : 0;
+    const float inv = wr > 0.0 ? (float)(1.0 / wr) : 0.0f;
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int m = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+        const int64_t c = c0 + (wv * BPW + b) * 32 + m;
+        if (!FULL && c >= cend) continue;
+        const float val = acc[b][nb][j];
+        if (fin) {
+          if (tg >= 0)
+            ov.cube[c * ov.ntarget + tg] = wr > 0.0 ? val * inv : __int_as_float(0x7fc00000);
+        } else if (ov.mode == ACC_ADD) {
+          ov.S[c * ns + slot] += val;
+        } else {
+          ov.S[c * ns + slot] = val;
+        }
+      }
+    }
+  }
+  if (c0 == 0 && t < kTile) {
+    const int64_t slot = tile * kTile + t;
+    if (fin) {
+      const int32_t tg = ov.slot_target[slot];
+      if (tg >= 0 && ov.wout) ov.wout[tg] = (float)s_wfin[0][t];
+    } else if (ov.mode == ACC_ADD) {
+      ov.W[slot] += s_wfin[0][t];
+      ov.Wn[slot] += s_wfin[1][t];
+    } else {
+      ov.W[slot] = s_wfin[0][t];
+      ov.Wn[slot] = s_wfin[1][t];
+    }
+  }
+}
+
+}  // namespace cg

@@ -51,18 +51,45 @@ hipError_t launch_prep(const double* lon, const double* lat, int64_t n, int64_t 
 // Per pass: block histograms (digit-major), one exclusive scan, and a
 // stable scatter that ranks keys inside each wavefront with ballots.
 
-__global__ void __launch_bounds__(kSortThreads) k_hist(const uint32_t* __restrict__ keys, int64_t n,
+constexpr int kMaxJobs = 256;   // the job pass sorts by one 8-bit digit
+
+// Digit of element i: 8 key bits at `shift`, or (JOB) the job holding the
+// value, i.e. its position in the concatenated order (job offsets in LDS).
+template <bool JOB>
+__device__ __forceinline__ uint32_t sort_digit(uint32_t key, uint32_t val, int shift,
+                                               const int64_t* s_off, int njobs) {
+  if constexpr (JOB) return (uint32_t)job_of(s_off, njobs, (int64_t)val);
+  else return (key >> shift) & 255u;
+}
+
+template <bool JOB>
+__device__ __forceinline__ void stage_job_offsets(int64_t* s_off, const int64_t* joff, int njobs) {
+  if constexpr (JOB) {
+    for (int k = threadIdx.x; k <= njobs; k += blockDim.x) s_off[k] = joff[k];
+    __syncthreads();
+  }
+}
+
+template <bool JOB>
+__global__ void __launch_bounds__(kSortThreads) k_hist(const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ vals, int64_t n,
                                                        int shift, uint32_t* __restrict__ hist,
-                                                       int64_t nblocks) {
+                                                       int64_t nblocks, const int64_t* joff,
+                                                       int njobs) {
   __shared__ uint32_t h[256];
+  __shared__ int64_t s_off[JOB ? kMaxJobs + 1 : 1];
   const int t = threadIdx.x;
   h[t] = 0;
+  stage_job_offsets<JOB>(s_off, joff, njobs);
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = base + (int64_t)r * kSortThreads + t;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    if (i < n) {
+      const uint32_t d = sort_digit<JOB>(JOB ? 0u : keys[i], JOB ? vals[i] : 0u, shift, s_off, njobs);
+      atomicAdd(&h[d], 1u);
+    }
   }
   __syncthreads();
   hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
@@ -94,14 +121,17 @@ __global__ void __launch_bounds__(256) k_digit_scan(uint32_t* __restrict__ hist,
   if (t == 0) totals[blockIdx.x] = carry;
 }
 
+template <bool JOB>
 __global__ void __launch_bounds__(kSortThreads) k_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int64_t nblocks,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* joff, int njobs) {
   constexpr int NW = kSortThreads / 64;
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[NW][256];
+  __shared__ int64_t s_off[JOB ? kMaxJobs + 1 : 1];
   const int t = threadIdx.x;
+  stage_job_offsets<JOB>(s_off, joff, njobs);
   const int lane = t & 63;
   const int w = t >> 6;
   // digit bases: exclusive scan of the 256 digit totals
@@ -126,7 +156,7 @@ __global__ void __launch_bounds__(kSortThreads) k_scatter(
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
     const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
+    const uint32_t d = valid ? sort_digit<JOB>(key, val, shift, s_off, njobs) : 0u;
     // lanes holding the same digit
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -166,25 +196,157 @@ size_t radix_hist_elems(int64_t n) {
   return (size_t)(nb < 1 ? 1 : nb) * 256 + 256;
 }
 
+static void sort_pass(bool job, uint32_t*& ki, uint32_t*& vi, uint32_t*& ko, uint32_t*& vo,
+                      uint32_t* hist, int64_t n, int64_t nb, int shift, const int64_t* joff,
+                      int njobs, hipStream_t st) {
+  uint32_t* totals = hist + nb * 256;
+  if (job) {
+    hipLaunchKernelGGL(k_hist<true>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, vi, n,
+                       shift, hist, nb, joff, njobs);
+  } else {
+    hipLaunchKernelGGL(k_hist<false>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, vi, n,
+                       shift, hist, nb, joff, njobs);
+  }
+  hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, hist, nb, totals);
+  if (job) {
+    hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, vi, n,
+                       shift, hist, totals, nb, ko, vo, joff, njobs);
+  } else {
+    hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, vi, n,
+                       shift, hist, totals, nb, ko, vo, joff, njobs);
+  }
+  uint32_t* tk = ki; ki = ko; ko = tk;
+  uint32_t* tv = vi; vi = vo; vo = tv;
+}
+
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                       uint32_t* hist, int64_t n, int bits, bool* result_in_tmp, hipStream_t st) {
+  return radix_sort_jobs(keys, vals, keys_tmp, vals_tmp, hist, n, bits, nullptr, 0, result_in_tmp,
+                         st);
+}
+
+hipError_t radix_sort_jobs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                           uint32_t* hist, int64_t n, int bits, const int64_t* noff, int njobs,
+                           bool* result_in_tmp, hipStream_t st) {
   *result_in_tmp = false;
   if (n <= 1) return hipSuccess;
+  if (njobs > kMaxJobs) return hipErrorInvalidValue;
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
   uint32_t *ki = keys, *vi = vals, *ko = keys_tmp, *vo = vals_tmp;
   bool in_tmp = false;
   for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, n, shift, hist,
-                       nb);
-    uint32_t* totals = hist + nb * 256;
-    hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, hist, nb, totals);
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, vi, n, shift,
-                       hist, totals, nb, ko, vo);
-    uint32_t* tk = ki; ki = ko; ko = tk;
-    uint32_t* tv = vi; vi = vo; vo = tv;
+    sort_pass(false, ki, vi, ko, vo, hist, n, nb, shift, noff, njobs, st);
+    in_tmp = !in_tmp;
+  }
+  if (njobs > 1) {
+    sort_pass(true, ki, vi, ko, vo, hist, n, nb, 0, noff, njobs, st);
     in_tmp = !in_tmp;
   }
   *result_in_tmp = in_tmp;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batches: the samples of all jobs in one concatenated order (job j at
+// [noff[j], noff[j + 1])), each keyed with its own job's nside.
+
+__global__ void __launch_bounds__(256) k_batch_prep(const BatchJob* __restrict__ jobs,
+                                                    const int64_t* __restrict__ noff, int njobs,
+                                                    int64_t ntot, uint32_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals, int* flag) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ntot) return;
+  const int j = job_of(noff, njobs, g);
+  const BatchJob& jb = jobs[j];
+  const int64_t i = g - jb.noff;
+  const double a = jb.lon[i];
+  const double d = jb.lat[i];
+  uint32_t key;
+  if (!(isfinite(a) && isfinite(d) && fabs(d) <= 90.0)) {
+    key = (uint32_t)hpx::npix(jb.nside);
+    atomicOr(flag, 1);
+  } else {
+    double am = fmod(a, 360.0);
+    if (am < 0.0) am += 360.0;
+    double sd, cd;
+    sincos(d * (hpx::kPi / 180.0), &sd, &cd);
+    key = (uint32_t)hpx::ang2pix_ring(jb.nside, sd, cd, am * (hpx::kPi / 180.0));
+  }
+  keys[g] = key;
+  vals[g] = (uint32_t)g;
+}
+
+hipError_t launch_batch_prep(const BatchJob* jobs, const int64_t* noff, int njobs, int64_t ntot,
+                             uint32_t* keys, uint32_t* vals, int* flag, hipStream_t st) {
+  if (ntot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, jobs,
+                     noff, njobs, ntot, keys, vals, flag);
+  return hipGetLastError();
+}
+
+// ring offsets of every job: entry e of job j (ring i = e - rooff[j]) is the
+// first position of the job's sorted run whose key is >= ring_start(i); entry
+// 4 nside is the end of its valid samples.
+__global__ void __launch_bounds__(256) k_batch_ring_offsets(const BatchJob* __restrict__ jobs,
+                                                            const int64_t* __restrict__ rooff,
+                                                            int njobs,
+                                                            const uint32_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ ring_off) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rooff[njobs]) return;
+  const int j = job_of(rooff, njobs, e);
+  const BatchJob& jb = jobs[j];
+  const int64_t i = e - rooff[j];
+  int64_t lo = jb.noff, hi = jb.noff + jb.n;
+  if (i > 0) {
+    const uint64_t target = (uint64_t)hpx::ring_start(jb.nside, i);
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((uint64_t)keys[mid] < target) lo = mid + 1;
+      else hi = mid;
+    }
+  }
+  ring_off[e] = (uint32_t)lo;
+}
+
+hipError_t launch_batch_ring_offsets(const BatchJob* jobs, const int64_t* rooff, int njobs,
+                                     int64_t nentries, const uint32_t* keys, uint32_t* ring_off,
+                                     hipStream_t st) {
+  if (nentries <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_ring_offsets, dim3((unsigned)((nentries + 255) / 256)), dim3(256), 0,
+                     st, jobs, rooff, njobs, keys, ring_off);
+  return hipGetLastError();
+}
+
+// sorted unit vectors of every job's valid samples
+__global__ void __launch_bounds__(256) k_batch_permute(const BatchJob* __restrict__ jobs,
+                                                       const int64_t* __restrict__ noff, int njobs,
+                                                       int64_t ntot,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ ring_off,
+                                                       double* __restrict__ sx) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ntot) return;
+  const int j = job_of(noff, njobs, p);
+  const BatchJob& jb = jobs[j];
+  if (p >= (int64_t)ring_off[jb.ro_off + 4 * jb.nside]) return;   // invalid samples sort last
+  const int64_t src = (int64_t)vals[p] - jb.noff;
+  double am = fmod(jb.lon[src], 360.0);
+  if (am < 0.0) am += 360.0;
+  double sa, ca, sd, cd;
+  sincos(am * (hpx::kPi / 180.0), &sa, &ca);
+  sincos(jb.lat[src] * (hpx::kPi / 180.0), &sd, &cd);
+  sx[p] = cd * ca;
+  sx[ntot + p] = cd * sa;
+  sx[2 * ntot + p] = sd;
+}
+
+hipError_t launch_batch_permute(const BatchJob* jobs, const int64_t* noff, int njobs, int64_t ntot,
+                                const uint32_t* vals, const uint32_t* ring_off, double* sx,
+                                hipStream_t st) {
+  if (ntot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_permute, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st,
+                     jobs, noff, njobs, ntot, vals, ring_off, sx);
   return hipGetLastError();
 }
 

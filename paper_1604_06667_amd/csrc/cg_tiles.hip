@@ -270,9 +270,9 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
 constexpr int kRangeThreads = 256;
 constexpr int kRangeWaves = kRangeThreads / 64;
 
-__global__ void __launch_bounds__(kRangeThreads) k_tile_ranges(
-    const double* __restrict__ caps, const double* __restrict__ txyz, int64_t nslots,
-    int64_t nside, double rho, const int32_t* __restrict__ ring_first,
+__device__ __forceinline__ void tile_ranges_body(
+    int64_t tile, const double* __restrict__ caps, const double* __restrict__ txyz,
+    int64_t nslots, int64_t nside, double rho, const int32_t* __restrict__ ring_first,
     const uint64_t* __restrict__ range_off, const uint32_t* __restrict__ keys,
     const uint32_t* __restrict__ ring_off, uint32_t* __restrict__ ranges,
     uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
@@ -282,7 +282,6 @@ __global__ void __launch_bounds__(kRangeThreads) k_tile_ranges(
   __shared__ int s_fl[kRangeWaves][kRangeThreads];
   __shared__ uint32_t s_wsum[kRangeWaves];
   __shared__ uint64_t s_wcnt[kRangeWaves];
-  const int64_t tile = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t off = range_off[tile];
   const int64_t nring = (int64_t)((range_off[tile + 1] - off) / 2);
@@ -395,6 +394,40 @@ __global__ void __launch_bounds__(kRangeThreads) k_tile_ranges(
   }
 }
 
+__global__ void __launch_bounds__(kRangeThreads) k_tile_ranges(
+    const double* __restrict__ caps, const double* __restrict__ txyz, int64_t nslots,
+    int64_t nside, double rho, const int32_t* __restrict__ ring_first,
+    const uint64_t* __restrict__ range_off, const uint32_t* __restrict__ keys,
+    const uint32_t* __restrict__ ring_off, uint32_t* __restrict__ ranges,
+    uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
+  tile_ranges_body(blockIdx.x, caps, txyz, nslots, nside, rho, ring_first, range_off, keys,
+                   ring_off, ranges, nranges, ncand);
+}
+
+// Batches: one block per tile of any job; the job's own tables, nside and
+// radius, its range slots at rbase and its ring offsets at ro_off.
+__global__ void __launch_bounds__(kRangeThreads) k_batch_tile_ranges(
+    const BatchJob* __restrict__ jobs, const int64_t* __restrict__ toff, int njobs,
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ring_off,
+    uint32_t* __restrict__ ranges, uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
+  const int64_t g = blockIdx.x;
+  const int j = job_of(toff, njobs, g);
+  const BatchJob& jb = jobs[j];
+  tile_ranges_body(g - jb.toff, jb.caps, jb.txyz, jb.nslots, jb.nside, jb.rho, jb.ring_first,
+                   jb.range_off, keys, ring_off + jb.ro_off, ranges + 2 * jb.rbase,
+                   nranges + jb.toff, ncand + jb.toff);
+}
+
+hipError_t launch_batch_tile_ranges(const BatchJob* jobs, const int64_t* toff, int njobs,
+                                    int64_t ntiles, const uint32_t* keys, const uint32_t* ring_off,
+                                    uint32_t* ranges, uint32_t* nranges, uint64_t* ncand,
+                                    hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_tile_ranges, dim3((unsigned)ntiles), dim3(kRangeThreads), 0, st, jobs,
+                     toff, njobs, keys, ring_off, ranges, nranges, ncand);
+  return hipGetLastError();
+}
+
 hipError_t launch_tile_ranges(const double* caps, const double* txyz, int64_t nslots,
                               int64_t ntiles, int64_t nside, double rho,
                               const int32_t* ring_first, const uint64_t* range_off,
@@ -411,30 +444,24 @@ hipError_t launch_tile_ranges(const double* caps, const double* txyz, int64_t ns
 // Expand each tile's ranges into its list of candidates: sorted position,
 // input index and unit vector, so the contraction reads them in one level.
 
-__global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ range_off,
-                                               const uint32_t* __restrict__ ranges,
-                                               const uint32_t* __restrict__ nranges,
-                                               const uint64_t* __restrict__ cand_off,
-                                               const uint32_t* __restrict__ vals,
-                                               const double* __restrict__ sx, int64_t nsorted,
-                                               uint32_t* __restrict__ cand,
-                                               uint32_t* __restrict__ crow,
-                                               double* __restrict__ cxyz, int64_t ncap) {
-  // One wavefront per tile.  Ranges are taken 64 at a time (one per lane);
-  // a wavefront scan of their lengths places them, then every lane writes
-  // one candidate per step, finding its range by binary search in LDS.
+// One wavefront per tile.  Ranges are taken 64 at a time (one per lane); a
+// wavefront scan of their lengths places them, then every lane writes one
+// candidate per step, finding its range by binary search in LDS.  The data
+// row of a candidate is its value minus row0 (the job's first position).
+__device__ __forceinline__ void expand_body(const uint32_t* __restrict__ ranges, uint32_t nr,
+                                            uint64_t out, const uint32_t* __restrict__ vals,
+                                            int64_t row0, const double* __restrict__ sx,
+                                            int64_t nsorted, uint32_t* __restrict__ cand,
+                                            uint32_t* __restrict__ crow,
+                                            double* __restrict__ cxyz, int64_t ncap) {
   __shared__ uint32_t s_start[64], s_b[64];
-  const int64_t tile = blockIdx.x;
   const int lane = threadIdx.x;
-  const uint64_t roff = range_off[tile];
-  const uint32_t nr = nranges[tile];
-  uint64_t out = cand_off[tile];
   for (uint32_t k0 = 0; k0 < nr; k0 += 64) {
     const uint32_t k = k0 + lane;
     uint32_t b = 0, len = 0;
     if (k < nr) {
-      b = ranges[2 * (roff + k)];
-      len = ranges[2 * (roff + k) + 1];
+      b = ranges[2 * k];
+      len = ranges[2 * k + 1];
     }
     uint32_t incl = len;
 #pragma unroll
@@ -457,7 +484,7 @@ __global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ rang
       const uint32_t pos = s_b[lo] + (p - s_start[lo]);
       const uint64_t o = out + p;
       cand[o] = pos;
-      crow[o] = vals[pos];
+      crow[o] = (uint32_t)((int64_t)vals[pos] - row0);
       cxyz[o] = sx[pos];
       cxyz[ncap + o] = sx[nsorted + pos];
       cxyz[2 * ncap + o] = sx[2 * nsorted + pos];
@@ -465,6 +492,62 @@ __global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ rang
     out += tot;
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ range_off,
+                                               const uint32_t* __restrict__ ranges,
+                                               const uint32_t* __restrict__ nranges,
+                                               const uint64_t* __restrict__ cand_off,
+                                               const uint32_t* __restrict__ vals,
+                                               const double* __restrict__ sx, int64_t nsorted,
+                                               uint32_t* __restrict__ cand,
+                                               uint32_t* __restrict__ crow,
+                                               double* __restrict__ cxyz, int64_t ncap) {
+  const int64_t tile = blockIdx.x;
+  expand_body(ranges + 2 * range_off[tile], nranges[tile], cand_off[tile], vals, 0, sx, nsorted,
+              cand, crow, cxyz, ncap);
+}
+
+__global__ void __launch_bounds__(64) k_batch_expand(
+    const BatchJob* __restrict__ jobs, const int64_t* __restrict__ toff, int njobs,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ nranges,
+    const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ vals,
+    const double* __restrict__ sx, int64_t nsorted, uint32_t* __restrict__ cand,
+    uint32_t* __restrict__ crow, double* __restrict__ cxyz, int64_t ncap,
+    const int* __restrict__ ovf) {
+  if (*ovf) return;   // candidate buffers too small: nothing is written
+  const int64_t g = blockIdx.x;
+  const int j = job_of(toff, njobs, g);
+  const BatchJob& jb = jobs[j];
+  expand_body(ranges + 2 * (jb.rbase + jb.range_off[g - jb.toff]), nranges[g], cand_off[g], vals,
+              jb.noff, sx, nsorted, cand, crow, cxyz, ncap);
+}
+
+// ovf[0]: this pass overflows the candidate buffers (cleared every pass);
+// ovf[1]: the same, sticky until the host reads it.
+__global__ void k_batch_guard(const uint64_t* __restrict__ cand_off, int64_t ntiles, int64_t cap,
+                              int* ovf) {
+  if (threadIdx.x == 0 && cand_off[ntiles] > (uint64_t)cap) {
+    ovf[0] = 1;
+    ovf[1] = 1;
+  }
+}
+
+hipError_t launch_batch_guard(const uint64_t* cand_off, int64_t ntiles, int64_t cap, int* ovf,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_guard, dim3(1), dim3(64), 0, st, cand_off, ntiles, cap, ovf);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_expand(const BatchJob* jobs, const int64_t* toff, int njobs, int64_t ntiles,
+                               const uint32_t* ranges, const uint32_t* nranges,
+                               const uint64_t* cand_off, const uint32_t* vals, const double* sx,
+                               int64_t nsorted, uint32_t* cand, uint32_t* crow, double* cxyz,
+                               int64_t ncap, const int* ovf, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_expand, dim3((unsigned)ntiles), dim3(64), 0, st, jobs, toff, njobs,
+                     ranges, nranges, cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap, ovf);
+  return hipGetLastError();
 }
 
 hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
