@@ -1,19 +1,33 @@
 #!/usr/bin/env python3
 """Throughput of the gridding hot path on one MI355X.
 
-One step = one pass of the whole path over the spectral-cube workload:
-HEALPix indexing, radix sort, ring offsets, per-tile candidate lookup, the
-contraction of Eq. (1)-(2) and the normalisation of Eq. (3), producing the
-normalised cube and the weight map (``cg_grid_datacube``).  Inputs are
-resident in device memory before the timed region starts.
+One step = one pass of the whole path over one workload: HEALPix indexing,
+radix sort, ring offsets, per-tile candidate lookup, the contraction of
+Eq. (1)-(2) and the normalisation of Eq. (3), producing the normalised cube
+and the weight map.  Inputs are resident in device memory before the timed
+region starts.
 
-Workload (spectral cube): 1,000,000 samples on a jittered raster scan (row
-spacing 1', jitter 0.2') over 10x10 deg around (120, 30) deg, 1024 FP32
-channels of Gaussian spectral lines plus noise, gridded onto a 600x600 SIN
-grid at 1' with a Gaussian kernel sigma = 1.5', support 3 sigma.
+Workloads (``--workload``; all synthetic, seeded):
+
+* ``cube`` (default): 1,000,000 samples on a jittered raster scan (row
+  spacing 1', jitter 0.2') over 10x10 deg around (120, 30) deg, 1024 FP32
+  channels of Gaussian spectral lines plus noise, onto a 600x600 SIN grid at
+  1'; Gaussian kernel sigma 1.5', support 3 sigma.  BF16 matrix-core
+  contraction, with the FP32 gather path timed beside it.
+* ``allsky``: 12,000,000 samples uniform on the sphere, 8 FP32 channels, onto
+  a 4320x2160 CAR grid at 5' (both poles, the 0/360 seam); sigma 6',
+  support 18', nside 1024; FP32 path.
+* ``batched``: 64 independent jobs of uneven size (5k-500k samples, grids
+  64^2-512^2 at 0.5'-3', 16-2048 BF16 channels, 25 % elliptical kernels) in
+  one batch: one lookup pass and one persistent matrix-core launch, tuned,
+  and replayed from a HIP graph.
+* ``sightlines``: 10,000,000 samples x 256 BF16 channels over 30x30 deg onto
+  2,000,000 arbitrary target positions, elliptical Gaussian 3'x2' PA 30 deg,
+  support 9', nside 4096; BF16, FP16 and FP32 contractions.
 
 Prints one JSON line.  ``value`` = sample-channel contributions per second =
-(number of (target, sample) pairs with d <= support) x channels / time per step.
+(number of (target, sample) pairs with d <= support) x channels / time per
+step.
 """
 from __future__ import annotations
 
@@ -33,8 +47,9 @@ sys.path.insert(0, HERE)
 METRIC = ("gridded sample-channel contributions/sec on 1 GPU, BF16-MFMA vs FP32 at "
           "≤2e-3 rel")
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
+PEAK_VALU_TFLOPS = 78.6   # FP32 (packed FP32 disabled) and FP64: 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_BF16_TFLOPS = 2500.0
+FLOPS_PER_PAIR = 12       # FP64 chord^2, support test, distance series per in-support pair
 
 
 def log(*a):
@@ -74,6 +89,21 @@ def traffic_from_profiles(kernel_tag):
     return None
 
 
+def roof_hbm(alg_bytes, kms, tag):
+    ach = alg_bytes / (kms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic_from_profiles(tag),
+            "kernel_ms": round(kms, 4), "alg_bytes": int(alg_bytes)}
+
+
+def roof_alu(flops, kms, tag):
+    ach = flops / (kms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_TFLOPS, 4),
+            "traffic": traffic_from_profiles(tag), "kernel_ms": round(kms, 4),
+            "alg_flops": float(flops)}
+
+
 def time_path(g, lon, lat, data, cube, weights, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -90,87 +120,114 @@ def time_path(g, lon, lat, data, cube, weights, steps, warmup):
     return (t1 - t0) * 1e3 / steps, (kms / max(nl, 1)), nl
 
 
-def cpu_baseline_and_error(wl, cube_by_prec, block):
-    """Oracle (FP64, cKDTree candidates + Vincenty) on a central block of
-    block x block targets with the samples that can reach them."""
+def oracle_sample(wl, tidx, margin_deg):
+    """Samples that can reach the targets tidx (a compact region), and the
+    oracle's result for those targets; returns (result, seconds, nsamples)."""
     import oracle
-    w = wl.target["wcs"]
-    nx, ny = w["naxis1"], w["naxis2"]
-    x0, y0 = (nx - block) // 2, (ny - block) // 2
-    xs, ys = np.meshgrid(np.arange(x0, x0 + block), np.arange(y0, y0 + block))
-    tidx = (ys * nx + xs).ravel()
+    import torch
     tlon, tlat = oracle.targets_of(wl)
     bl, bb = tlon[tidx], tlat[tidx]
-    m = wl.support + 0.02
-    clat = math.cos(math.radians(max(abs(bb.min()), abs(bb.max())) + m))
-    sel = ((wl.lat >= bb.min() - m) & (wl.lat <= bb.max() + m) &
-           (np.abs(((wl.lon - bl.mean() + 180) % 360) - 180) <= (bl.max() - bl.min()) / 2 + m / clat))
+    ok = np.isfinite(bl) & np.isfinite(bb)
+    bl, bb, tidx = bl[ok], bb[ok], tidx[ok]
+    m = wl.support + margin_deg
+    lat_hi = min(90.0, bb.max() + m)
+    lat_lo = max(-90.0, bb.min() - m)
+    clat = math.cos(math.radians(max(abs(lat_lo), abs(lat_hi))))
+    ref_lon = math.degrees(math.atan2(np.sin(np.radians(bl)).mean(), np.cos(np.radians(bl)).mean()))
+    dl = ((bl - ref_lon + 180.0) % 360.0) - 180.0
+    half = max(abs(dl.min()), abs(dl.max())) + m / max(clat, 1e-6)
+    sl = ((wl.lon - ref_lon + 180.0) % 360.0) - 180.0
+    sel = (wl.lat >= lat_lo) & (wl.lat <= lat_hi)
+    if lat_hi < 89.9 and lat_lo > -89.9 and half < 180.0:
+        sel &= np.abs(sl) <= half
     sidx = np.nonzero(sel)[0]
-    import torch
     data = wl.data[torch.as_tensor(sidx, device=wl.data.device)].to("cpu", torch.float64).numpy()
     t0 = time.perf_counter()
     ref = oracle.grid_kdtree(wl.lon[sidx], wl.lat[sidx], data, bl, bb, wl.kernel, wl.support)
     dt = time.perf_counter() - t0
+    return ref, tidx, dt, sidx.size
+
+
+def cpu_baseline(wl, tidx, desc, cubes, margin_deg=0.02):
+    """Oracle (FP64, cKDTree candidates + Vincenty, one thread) on a bounded
+    sample of the workload's targets; also the e_val of each GPU cube there."""
+    import oracle
+    import torch
+    ref, tidx, dt, ns = oracle_sample(wl, tidx, margin_deg)
     contrib = float(ref["count"].sum()) * wl.nchan
     errs = {}
-    for prec, cube in cube_by_prec.items():
+    for prec, cube in cubes.items():
         R = cube.reshape(wl.nchan, -1)[:, torch.as_tensor(tidx, device=cube.device)]
-        R = R.to("cpu", torch.float64).numpy()
-        errs[prec] = oracle.e_val(R, ref["R"], ref["W"])
-    return {"value": contrib / dt, "unit": "contributions/s", "cores": 1, "kind": "oracle",
-            "sample": (f"central {block}x{block} targets of the 600x600 grid with the "
-                       f"{sidx.size} samples that can reach them; FP64 NumPy/SciPy "
-                       f"(cKDTree ball query + Vincenty), single thread, {dt:.1f} s"),
-            "seconds": round(dt, 2)}, errs
+        errs[prec] = float(f"{oracle.e_val(R.to('cpu', torch.float64).numpy(), ref['R'], ref['W']):.3e}")
+    cpu = {"value": contrib / dt, "unit": "contributions/s", "cores": 1, "kind": "oracle",
+           "sample": (f"{desc}: {tidx.size} targets with the {ns} samples that can reach "
+                      f"them; FP64 NumPy/SciPy (cKDTree ball query + Vincenty), single "
+                      f"thread, {dt:.1f} s"),
+           "seconds": round(dt, 2)}
+    log(f"cpu oracle: {cpu['value']:.3e} contributions/s in {dt:.1f}s; e_val {errs}")
+    return cpu, errs
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "bf16", "fp16"])
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
-    ap.add_argument("--cpu-block", type=int, default=384)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device copy (counter calibration)")
-    a = ap.parse_args()
-    if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              f"(requested --gpus {a.gpus}); see DESIGN.md for how the path would shard.",
-              file=sys.stderr)
-        sys.exit(2)
+def device_inputs(wl, dev):
+    import torch
+    lon = torch.as_tensor(wl.lon, dtype=torch.float64, device=dev)
+    lat = torch.as_tensor(wl.lat, dtype=torch.float64, device=dev)
+    data = wl.data if wl.data.device.type == "cuda" else wl.data.to(dev)
+    if wl.dtype == "bf16":
+        data = data.to(torch.bfloat16)
+    return lon, lat, data.contiguous()
 
+
+def make_gridder(wl, dev):
+    import torch
+    import paper_1604_06667_amd as cgp
+    if wl.target["kind"] == "wcs":
+        g = cgp.WcsGrid(header_of(wl.target["wcs"], wl.nchan))
+    else:
+        tl = torch.as_tensor(np.asarray(wl.target["lon"], dtype=np.float64), device=dev)
+        tb = torch.as_tensor(np.asarray(wl.target["lat"], dtype=np.float64), device=dev)
+        g = cgp.SlGrid(tl, tb, wl.nchan)
+    kind, params = wl.kernel
+    if wl.nside is not None:
+        g.set_nside(wl.nside)
+    res = wl.hpx_maxres or (0.5 * (params[0] if kind == "gauss1d" else params[1]))
+    g.set_kernel(kind, params, wl.support, res)
+    return g
+
+
+def count_contributions(g, lon, lat, nchan):
+    import torch
+    counts, _ = g.neighbour_stats(lon, lat)
+    pairs = int(counts.to(torch.int64).sum().item())
+    return pairs, pairs * nchan
+
+
+def base_line(a, wl_desc, value, ms, dtype, config, roof, cpu):
+    return {"metric": METRIC, "value": value, "unit": "contributions/s",
+            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic",
+            "config": dict({"workload": wl_desc}, **config),
+            "roofline": roof, "cpu_baseline": cpu}
+
+
+DT = {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}
+
+
+# ------------------------------------------------------------------ workloads
+
+def run_cube(a, dev):
     import torch
     import synth
     import paper_1604_06667_amd as cgp
-
-    if a.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 3}))
-        return
-
-    dev = "cuda:0"
     t0 = time.time()
     wl = synth.config2(device=dev)
-    lon = torch.as_tensor(wl.lon, dtype=torch.float64, device=dev)
-    lat = torch.as_tensor(wl.lat, dtype=torch.float64, device=dev)
-    data = wl.data
+    lon, lat, data = device_inputs(wl, dev)
     torch.cuda.synchronize()
     log(f"workload built in {time.time() - t0:.1f}s: {wl.name}")
-
-    g = cgp.WcsGrid(header_of(wl.target["wcs"], wl.nchan))
-    g.set_kernel(*wl.kernel, wl.support, wl.hpx_maxres)
-    counts, _ = g.neighbour_stats(lon, lat)
-    pairs = int(counts.to(torch.int64).sum().item())
-    contributions = pairs * wl.nchan
+    g = make_gridder(wl, dev)
+    pairs, contributions = count_contributions(g, lon, lat, wl.nchan)
     ntarget = wl.ntargets()
-
     headline = a.prec
     if headline == "auto":
         try:
@@ -184,7 +241,6 @@ def main():
     ms, kms, nl = time_path(g, lon, lat, data, cube, weights, a.steps, a.warmup)
     log(f"{headline}: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
     cubes = {headline: cube.clone()}
-
     extra = {}
     if headline != "fp32" and not a.no_compare:
         g.set_precision("fp32")
@@ -194,50 +250,233 @@ def main():
                               "kernel_ms": round(kms32, 4)}
         extra["speedup_vs_fp32"] = round(ms32 / ms, 3)
         log(f"fp32: {ms32:.3f} ms/step, kernel {kms32:.3f} ms")
-
-    # roofline of the contraction kernel
-    in_bytes = wl.nsamples * (wl.nchan * data.element_size() + 24)
-    out_bytes = ntarget * (wl.nchan * 4 + 4)
-    alg_bytes = in_bytes + out_bytes
+    alg_bytes = wl.nsamples * (wl.nchan * data.element_size() + 24) + ntarget * (wl.nchan * 4 + 4)
     if headline == "fp32":
-        flops = 2.0 * contributions
-        ach = flops / (kms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 4)}
+        roof = roof_alu(2.0 * contributions + FLOPS_PER_PAIR * pairs, kms, "contraction_fp32")
     else:
-        ach = alg_bytes / (kms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4)}
-    roof["traffic"] = traffic_from_profiles(f"contraction_{headline}")
-    roof["kernel_ms"] = round(kms, 4)
-    roof["alg_bytes"] = alg_bytes
-
+        roof = roof_hbm(alg_bytes, kms, f"contraction_{headline}")
     cpu = None
     if not a.no_cpu:
-        cpu, errs = cpu_baseline_and_error(wl, cubes, a.cpu_block)
-        extra["e_val"] = {k: float(f"{v:.3e}") for k, v in errs.items()}
-        log(f"cpu oracle: {cpu['value']:.3e} contributions/s; e_val {errs}")
-
-    out = {
-        "metric": METRIC,
-        "value": contributions / (ms / 1e3),
-        "unit": "contributions/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[headline],
-        "data": "synthetic",
-        "config": {"workload": ("spectral cube: 1,000,000 jittered-raster samples x 1024 FP32 "
-                                "channels -> 600x600 SIN grid at 1', gauss1d sigma 1.5', "
-                                "support 4.5'"),
-                   "samples": wl.nsamples, "targets": ntarget, "channels": wl.nchan,
-                   "nside": g.nside, "pairs": pairs, "contributions": contributions,
-                   "contraction": headline},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
+        b = a.cpu_block
+        x0 = (600 - b) // 2
+        xs, ys = np.meshgrid(np.arange(x0, x0 + b), np.arange(x0, x0 + b))
+        cpu, errs = cpu_baseline(wl, (ys * 600 + xs).ravel(),
+                                 f"central {b}x{b} targets of the 600x600 grid", cubes)
+        extra["e_val"] = errs
+    out = base_line(a, ("spectral cube: 1,000,000 jittered-raster samples x 1024 FP32 channels "
+                        "-> 600x600 SIN grid at 1', gauss1d sigma 1.5', support 4.5'"),
+                    contributions / (ms / 1e3), ms, DT[headline],
+                    {"samples": wl.nsamples, "targets": ntarget, "channels": wl.nchan,
+                     "nside": g.nside, "pairs": pairs, "contributions": contributions,
+                     "contraction": headline}, roof, cpu)
     out.update(extra)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def run_allsky(a, dev):
+    import torch
+    import synth
+    t0 = time.time()
+    wl = synth.config3(device=dev)
+    lon, lat, data = device_inputs(wl, dev)
+    torch.cuda.synchronize()
+    log(f"workload built in {time.time() - t0:.1f}s: {wl.name}")
+    g = make_gridder(wl, dev)
+    g.set_precision("fp32")
+    pairs, contributions = count_contributions(g, lon, lat, wl.nchan)
+    nx, ny = wl.target["wcs"]["naxis1"], wl.target["wcs"]["naxis2"]
+    cube = torch.empty((wl.nchan, ny, nx), dtype=torch.float32, device=dev)
+    weights = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    ms, kms, nl = time_path(g, lon, lat, data, cube, weights, a.steps, a.warmup)
+    log(f"fp32: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
+    roof = roof_alu(2.0 * contributions + FLOPS_PER_PAIR * pairs, kms, "contraction_allsky_fp32")
+    roof["alg_bytes"] = int(wl.nsamples * (wl.nchan * 4 + 16) + nx * ny * (wl.nchan * 4 + 4))
+    cpu, extra = None, {}
+    if not a.no_cpu:
+        # a block of targets across the 0/360 seam on the equator
+        k = 256
+        y0, x0 = ny // 2 - k // 2, nx // 2 - k // 2
+        xs, ys = np.meshgrid(np.arange(x0, x0 + k), np.arange(y0, y0 + k))
+        cpu, errs = cpu_baseline(wl, (ys * nx + xs).ravel(),
+                                 f"{k}x{k} targets across the 0/360 seam on the equator",
+                                 {"fp32": cube})
+        extra["e_val"] = errs
+    out = base_line(a, ("all-sky map: 12,000,000 uniform samples x 8 FP32 channels -> 4320x2160 "
+                        "CAR at 5', gauss1d sigma 6', support 18', nside 1024"),
+                    contributions / (ms / 1e3), ms, "f32",
+                    {"samples": wl.nsamples, "targets": nx * ny, "channels": wl.nchan,
+                     "nside": g.nside, "pairs": pairs, "contributions": contributions,
+                     "contraction": "fp32"}, roof, cpu)
+    out.update(extra)
+    return out
+
+
+def run_sightlines(a, dev):
+    import torch
+    import synth
+    t0 = time.time()
+    wl = synth.config5(device=dev)
+    lon, lat, data = device_inputs(wl, dev)
+    torch.cuda.synchronize()
+    log(f"workload built in {time.time() - t0:.1f}s: {wl.name}")
+    g = make_gridder(wl, dev)
+    g.set_precision("bf16")
+    pairs, contributions = count_contributions(g, lon, lat, wl.nchan)
+    nt = wl.ntargets()
+    cube = torch.empty((wl.nchan, nt), dtype=torch.float32, device=dev)
+    weights = torch.empty((nt,), dtype=torch.float32, device=dev)
+    res, cubes = {}, {}
+    for prec in ["bf16", "fp16", "fp32"]:
+        if prec == "fp32" and a.no_compare:
+            continue
+        g.set_precision(prec)
+        st = a.steps if prec != "fp32" else max(2, a.steps // 2)
+        ms, kms, nl = time_path(g, lon, lat, data, cube, weights, st, 1 if prec == "fp32" else a.warmup)
+        res[prec] = (ms, kms)
+        cubes[prec] = cube.clone()
+        log(f"{prec}: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
+    ms, kms = res["bf16"]
+    alg_bytes = (wl.nsamples * (wl.nchan * data.element_size() + 16) + nt * 16 +
+                 nt * (wl.nchan * 4 + 4))
+    roof = roof_hbm(alg_bytes, kms, "contraction_sightlines_bf16")
+    extra = {"paths": {p: {"value": contributions / (m / 1e3), "ms_per_step": round(m, 4),
+                           "kernel_ms": round(k, 4)} for p, (m, k) in res.items()}}
+    if "fp32" in res:
+        extra["speedup_vs_fp32"] = round(res["fp32"][0] / ms, 3)
+    cpu = None
+    if not a.no_cpu:
+        # targets in a 1.2 x 1.2 deg box at the field centre
+        tl, tb = np.asarray(wl.target["lon"]), np.asarray(wl.target["lat"])
+        sel = np.nonzero((np.abs(tl - 120.0) < 0.6) & (np.abs(tb - 30.0) < 0.6))[0]
+        cpu, errs = cpu_baseline(wl, sel, "sight lines in a 1.2x1.2 deg box at (120, 30)", cubes)
+        extra["e_val"] = errs
+    out = base_line(a, ("sight lines: 10,000,000 samples x 256 BF16 channels over 30x30 deg -> "
+                        "2,000,000 targets, gauss2d 3'x2' PA 30, support 9', nside 4096"),
+                    contributions / (ms / 1e3), ms, "bf16",
+                    {"samples": wl.nsamples, "targets": nt, "channels": wl.nchan,
+                     "nside": g.nside, "pairs": pairs, "contributions": contributions,
+                     "contraction": "bf16"}, roof, cpu)
+    out.update(extra)
+    return out
+
+
+def run_batched(a, dev):
+    import torch
+    import synth
+    import paper_1604_06667_amd as cgp
+    t0 = time.time()
+    wls = synth.config4(device=dev)
+    ins = [device_inputs(wl, dev) for wl in wls]
+    torch.cuda.synchronize()
+    log(f"workload built in {time.time() - t0:.1f}s: {len(wls)} jobs, "
+        f"{sum(w.nsamples for w in wls)} samples")
+    gs = []
+    pairs = contributions = 0
+    alg_bytes = 0
+    for wl, (lon, lat, d) in zip(wls, ins):
+        g = make_gridder(wl, dev)
+        g.set_precision("bf16")
+        p, c = count_contributions(g, lon, lat, wl.nchan)
+        pairs += p
+        contributions += c
+        alg_bytes += wl.nsamples * (wl.nchan * 2 + 16) + wl.ntargets() * (wl.nchan * 4 + 4)
+        gs.append(g)
+    b = cgp.Batch(gs, torch.bfloat16)
+    outs = b.outputs()
+    t0 = time.time()
+    b.tune(ins, outs, reps=2)
+    log(f"tuned in {time.time() - t0:.1f}s: rows/workgroup={b.query(5)} half={b.query(6)} "
+        f"wg/CU={b.query(7)} items={b.query(3)}")
+    # eager passes (one host synchronisation each)
+    for _ in range(a.warmup):
+        b.grid(ins, outs)
+    torch.cuda.synchronize()
+    b.profile(True)
+    t1 = time.perf_counter()
+    for _ in range(a.steps):
+        b.grid(ins, outs)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t1) * 1e3 / a.steps
+    nl, ktot = b.profile_read()
+    kms = ktot / max(nl, 1)
+    b.profile(False)
+    # graph replays (no host synchronisation)
+    b.capture(ins, outs)
+    for _ in range(a.warmup):
+        b.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(a.steps):
+        b.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / a.steps
+    b.sync()
+    log(f"batched: eager {ms_eager:.3f} ms/step (contraction {kms:.3f} ms), graph {ms:.3f} ms/step")
+    roof = roof_hbm(alg_bytes, kms, "contraction_batched_bf16")
+    extra = {"eager": {"value": contributions / (ms_eager / 1e3), "ms_per_step": round(ms_eager, 4)},
+             "tuned": {"rows_per_workgroup": b.query(5), "half_items": b.query(6),
+                       "workgroups_per_cu": b.query(7), "items": b.query(3)}}
+    cpu = None
+    if not a.no_cpu:
+        # the largest job's central 48x48 targets
+        j = int(np.argmax([wl.nsamples for wl in wls]))
+        wl = wls[j]
+        nx = wl.target["wcs"]["naxis1"]
+        ny = wl.target["wcs"]["naxis2"]
+        k = min(48, nx, ny)
+        x0, y0 = (nx - k) // 2, (ny - k) // 2
+        xs, ys = np.meshgrid(np.arange(x0, x0 + k), np.arange(y0, y0 + k))
+        cpu, errs = cpu_baseline(wl, (ys * nx + xs).ravel(),
+                                 f"job {j} (the largest): central {k}x{k} targets",
+                                 {"bf16": outs[j][0]})
+        extra["e_val"] = errs
+    out = base_line(a, ("batched: 64 jobs, 5k-500k samples, 64^2-512^2 SIN grids, 16-2048 BF16 "
+                        "channels, 25% elliptical; one lookup pass + one persistent launch, "
+                        "graph replay"),
+                    contributions / (ms / 1e3), ms, "bf16",
+                    {"jobs": len(wls), "samples": int(sum(w.nsamples for w in wls)),
+                     "targets": int(sum(w.ntargets() for w in wls)), "pairs": pairs,
+                     "contributions": contributions, "contraction": "bf16"}, roof, cpu)
+    out.update(extra)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube",
+                    choices=["cube", "allsky", "batched", "sightlines"])
+    ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "bf16", "fp16"],
+                    help="contraction of the cube workload")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
+    ap.add_argument("--cpu-block", type=int, default=384)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(requested --gpus {a.gpus}); see DESIGN.md for how the path would shard.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if a.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 3}))
+        return
+
+    dev = "cuda:0"
+    run = {"cube": run_cube, "allsky": run_allsky, "batched": run_batched,
+           "sightlines": run_sightlines}[a.workload]
+    print(json.dumps(run(a, dev)), flush=True)
 
 
 if __name__ == "__main__":
