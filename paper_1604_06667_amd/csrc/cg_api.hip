@@ -36,9 +36,8 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
   CG_HIP(cg::launch_permute(g->sorted_vals, roff + 4 * nside, n, lon, lat, data, dtype, ld,
                             g->nchan, with_data, n, g->sx.as<double>(), g->sdata.as<float>(), st),
          "permute");
-  CG_HIP(cg::launch_tile_ranges(g->caps.as<double>(), g->txyz.as<double>(), g->nslots, g->ntiles,
-                                nside, g->support_rad + 1e-9, g->ring_first.as<int32_t>(),
-                                g->range_off.as<uint64_t>(),
+  CG_HIP(cg::launch_tile_ranges(g->ntiles, g->ring_first.as<int32_t>(),
+                                g->range_off.as<uint64_t>(), g->win.as<uint32_t>(),
                                 g->sorted_keys, roff, g->ranges.as<uint32_t>(),
                                 g->nranges.as<uint32_t>(), g->ncand.as<uint64_t>(), st),
          "tile ranges");
@@ -470,7 +469,7 @@ void cg_destroy(cg_gridder* g) {
     (void)hipEventDestroy(e.second);
   }
   DevBuf* bufs[] = {&g->txyz, &g->tll, &g->slot_target, &g->target_slot, &g->caps,
-                    &g->ring_first, &g->span_bound, &g->range_off, &g->S, &g->W, &g->Wn, &g->flag, &g->zrow,
+                    &g->ring_first, &g->span_bound, &g->range_off, &g->win, &g->S, &g->W, &g->Wn, &g->flag, &g->zrow,
                     &g->keys, &g->vals, &g->keys2, &g->vals2, &g->hist, &g->ring_off, &g->sx,
                     &g->sdata, &g->ranges, &g->nranges, &g->ncand, &g->cand_off, &g->cand,
                     &g->crow, &g->cxyz};

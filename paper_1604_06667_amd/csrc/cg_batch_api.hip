@@ -202,6 +202,7 @@ cg_status upload_tables(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
     q.caps = g->caps.as<double>();
     q.ring_first = g->ring_first.as<int32_t>();
     q.range_off = g->range_off.as<uint64_t>();
+    q.win = g->win.as<uint32_t>();
     q.slot_target = g->slot_target.as<int32_t>();
     q.cube = in[j].cube_out;
     q.wout = in[j].weights_out;

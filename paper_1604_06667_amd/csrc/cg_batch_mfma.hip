@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kBatchWaves * 64) k_batch_mfma(
     const int64_t it = s_item;
     if (it >= nitems) break;
     const BatchItem item = items[it];
-    const BatchJob& jb = jobs[item.job];
+    const BatchJob& jb = jobs[item.job];   // global memory, not a kernel argument
     TileView tv;
     tv.txyz = jb.txyz;
     tv.tll = jb.tll;

@@ -92,7 +92,7 @@ struct cg_gridder {
   bool nside_fixed = false;
   int prec = CG_PREC_FP32;
   bool span_valid = false;
-  cgh::DevBuf ring_first, span_bound, range_off;
+  cgh::DevBuf ring_first, span_bound, range_off, win;
   int64_t total_ranges = 0;
   cgh::DevBuf S, W, Wn;
   bool fresh = true;
@@ -160,6 +160,12 @@ inline cg_status ensure_span(cg_gridder* g, hipStream_t st) {
   CG_HIP(ensure(g->nranges, sizeof(uint32_t) * (nt > 0 ? nt : 1)), "alloc ranges");
   CG_HIP(ensure(g->ncand, sizeof(uint64_t) * (nt > 0 ? nt : 1)), "alloc ranges");
   CG_HIP(ensure(g->cand_off, sizeof(uint64_t) * (nt + 1)), "alloc ranges");
+  CG_HIP(ensure(g->win, sizeof(uint32_t) * 2 * (g->total_ranges > 0 ? g->total_ranges : 1)),
+         "alloc windows");
+  CG_HIP(cg::launch_tile_windows(g->caps.as<double>(), g->txyz.as<double>(), g->nslots, nt,
+                                 g->nside, g->support_rad + 1e-9, g->ring_first.as<int32_t>(),
+                                 g->range_off.as<uint64_t>(), g->win.as<uint32_t>(), st),
+         "tile windows");
   g->span_valid = true;
   return CG_OK;
 }

@@ -62,16 +62,22 @@ __device__ __forceinline__ void work_of_block(int64_t b, int64_t ntiles, int64_t
 // ---------------------------------------------------------------- device math
 
 // (2 asin(c/2))^2 from the squared chord c^2: the true angular distance
-// squared.  Chords up to 0.35 rad (about 20 deg) use the series
-//   d^2 = c^2 (1 + c^2/12 + c^4/90 + c^6/560 + c^8/3150 + c^10/16632),
-// whose truncation error is below 1e-10 relative there (and below FP64
-// rounding for chords under 3 deg); longer chords take the exact form in a
-// separate function, which keeps the hot loops small.
+// squared, from the series
+//   d^2 = c^2 (1 + c^2/12 + c^4/90 + c^6/560 + c^8/3150 + c^10/16632 + ...)
+// (4 asin^2(x/2) = sum_n 2 x^(2n) / (n^2 C(2n, n))), whose truncation error is
+// below 1e-10 relative for chords up to 0.35 rad (about 20 deg).  The
+// correction c^2 (c^2/12 + ...) is at most 1.1 % of c^2, so it is evaluated
+// in FP32 (its rounding moves d^2 by < 1e-9 relative) and added to c^2 with
+// one FP64 fma: no FP64 constants, which keeps the hot loops' registers
+// free.  Longer chords take the exact form in a separate function.
 __device__ __noinline__ double chord2_to_d2_exact(double c2);
 __device__ __forceinline__ double chord2_to_d2(double c2) {
   if (c2 <= 0.1225) {
-    return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0 +
-                 c2 * (1.0 / 3150.0 + c2 * (1.0 / 16632.0))))));
+    const float c = (float)c2;
+    const float corr =
+        c * (1.0f / 12.0f + c * (1.0f / 90.0f + c * (1.0f / 560.0f +
+             c * (1.0f / 3150.0f + c * (1.0f / 16632.0f)))));
+    return fma(c2, (double)corr, c2);
   }
   return chord2_to_d2_exact(c2);
 }
@@ -133,9 +139,15 @@ hipError_t launch_tile_caps(const double* txyz, int64_t nslots, int64_t ntiles, 
                             hipStream_t st);
 hipError_t launch_tile_span(const double* caps, int64_t ntiles, int64_t nside, double rho_extra,
                             int32_t* ring_first, uint64_t* span_bound, hipStream_t st);
-hipError_t launch_tile_ranges(const double* caps, const double* txyz, int64_t nslots,
-                              int64_t ntiles, int64_t nside, double rho,
-                              const int32_t* ring_first, const uint64_t* range_off,
+// Pixel windows of every tile's rings (set-up): win[2 * s] = lo, win[2 * s + 1]
+// = hi (RING pixel indices, lo > hi when empty) for the range slots s of
+// range_off, two per ring.
+hipError_t launch_tile_windows(const double* caps, const double* txyz, int64_t nslots,
+                               int64_t ntiles, int64_t nside, double rho,
+                               const int32_t* ring_first, const uint64_t* range_off,
+                               uint32_t* win, hipStream_t st);
+hipError_t launch_tile_ranges(int64_t ntiles, const int32_t* ring_first,
+                              const uint64_t* range_off, const uint32_t* win,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st);
 hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
@@ -182,6 +194,7 @@ struct BatchJob {
   const double* caps;
   const int32_t* ring_first;
   const uint64_t* range_off;   // [ntiles + 1] job-local range-slot offsets
+  const uint32_t* win;         // pixel windows of the range slots
   const int32_t* slot_target;
   float* cube;                 // [nchan][ntarget] normalised output
   float* wout;                 // [ntarget] weight map (may be null)

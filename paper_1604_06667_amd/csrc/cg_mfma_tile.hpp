@@ -107,10 +107,11 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, int nvalid, bool 
 // at a row of zeros, so the loads need no bounds selects.  FULL: the channel
 // count is a multiple of CP (no channel bounds checks).
 template <int NW, int BPW, int KT, int MODE, bool FULL, typename T>
-__device__ __forceinline__ void mfma_tile(const TileView& tv, const KernelParams& kp,
+__device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams kp,
                                           const T* __restrict__ data, const T* __restrict__ zrow,
-                                          int64_t ld, int64_t nchan, const OutView& ov,
+                                          int64_t ld, int64_t nchan, const OutView ov,
                                           int64_t tile, int64_t c0, int64_t cend) {
+  // (by value: a reference to a kernel argument would place it in scratch)
   constexpr bool F16 = MODE == 1;
   constexpr bool SPLIT = MODE == 0;
   constexpr bool BF16IN = std::is_same<T, uint16_t>::value;
@@ -345,30 +346,46 @@ __device__ __forceinline__ void mfma_tile(const TileView& tv, const KernelParams
   }
   __syncthreads();
 
-  // outputs: lane holds target n = nb*32 + lane%32, channels m = 8(j/4) + 4(lane/32) + j%4
+  // outputs: lane holds target n = nb*32 + lane%32, channels m = 8(j/4) + 4(lane/32) + j%4;
+  // one loop nest per (uniform) output mode, one lane test per target
   const bool fin = ov.mode == ACC_FINAL;
+  if (fin) {
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int n = nb * 32 + (lane & 31);
-    const int64_t slot = tile * kTile + n;
-    const double wr = s_wfin[1][n];
-    const int32_t tg = fin ? ov.slot_target[slot] : 0;
-    const float inv = wr > 0.0 ? (float)(1.0 / wr) : 0.0f;
+    for (int nb = 0; nb < 2; ++nb) {
+      const int n = nb * 32 + (lane & 31);
+      const int32_t tg = ov.slot_target[tile * kTile + n];
+      if (tg >= 0) {
+        const double wr = s_wfin[1][n];
+        const float inv = wr > 0.0 ? (float)(1.0 / wr) : 0.0f;
+        const bool filled = wr > 0.0;
+        float* __restrict__ dst = ov.cube + tg;
 #pragma unroll
-    for (int b = 0; b < BPW; ++b) {
+        for (int b = 0; b < BPW; ++b) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int m = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-        const int64_t c = c0 + (wv * BPW + b) * 32 + m;
-        if (!FULL && c >= cend) continue;
-        const float val = acc[b][nb][j];
-        if (fin) {
-          if (tg >= 0)
-            ov.cube[c * ov.ntarget + tg] = wr > 0.0 ? val * inv : __int_as_float(0x7fc00000);
-        } else if (ov.mode == ACC_ADD) {
-          ov.S[c * ns + slot] += val;
-        } else {
-          ov.S[c * ns + slot] = val;
+          for (int j = 0; j < 16; ++j) {
+            const int m = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+            const int64_t c = c0 + (wv * BPW + b) * 32 + m;
+            if (!FULL && c >= cend) continue;
+            dst[c * ov.ntarget] = filled ? acc[b][nb][j] * inv : __int_as_float(0x7fc00000);
+          }
+        }
+      }
+    }
+  } else {
+    const bool add = ov.mode == ACC_ADD;
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int64_t slot = tile * kTile + nb * 32 + (lane & 31);
+      float* __restrict__ dst = ov.S + slot;
+#pragma unroll
+      for (int b = 0; b < BPW; ++b) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int m = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+          const int64_t c = c0 + (wv * BPW + b) * 32 + m;
+          if (!FULL && c >= cend) continue;
+          if (add) dst[c * ns] += acc[b][nb][j];
+          else dst[c * ns] = acc[b][nb][j];
         }
       }
     }

@@ -246,42 +246,27 @@ hipError_t launch_tile_span(const double* caps, int64_t ntiles, int64_t nside, d
 }
 
 // ---------------------------------------------------------------------------
-// Candidate ranges: one 256-thread block per tile.  For each ring crossing
-// the tile's widened cap, the longitude window is the union over the tile's
-// targets of the window of each target's own support disk, which is tighter
-// than the window of the cap around the whole tile.  The targets' disks are
-// prepared once into LDS.  Rings are taken 256 at a time: first each
-// wavefront forms, for every ring of the batch, the union over its quarter of
-// the targets; then one thread per ring merges the four partial windows,
-// turns the window into pixel ranges, finds the sample ranges with two binary
-// searches in the ring's sorted segment and writes them at positions given by
-// a block-wide scan, in ring order.
-
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, uint32_t lo,
-                                                    uint32_t hi, uint64_t v) {
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if ((uint64_t)keys[mid] < v) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
+// Pixel windows of the tiles (set-up: they depend only on the targets, the
+// support and nside).  For each ring crossing a tile's widened cap, the
+// longitude window is the union over the tile's targets of the window of
+// each target's own support disk, which is tighter than the window of the
+// cap around the whole tile.  One 256-thread block per tile: the targets'
+// disks are prepared into LDS; rings are taken 256 at a time, each wavefront
+// forms for every ring the union over its quarter of the targets, then one
+// thread per ring merges the four partial windows and stores up to two RING
+// pixel ranges in the ring's two slots (an empty slot holds lo > hi).
 
 constexpr int kRangeThreads = 256;
 constexpr int kRangeWaves = kRangeThreads / 64;
 
-__device__ __forceinline__ void tile_ranges_body(
+__device__ __forceinline__ void tile_windows_body(
     int64_t tile, const double* __restrict__ caps, const double* __restrict__ txyz,
     int64_t nslots, int64_t nside, double rho, const int32_t* __restrict__ ring_first,
-    const uint64_t* __restrict__ range_off, const uint32_t* __restrict__ keys,
-    const uint32_t* __restrict__ ring_off, uint32_t* __restrict__ ranges,
-    uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
+    const uint64_t* __restrict__ range_off, uint32_t* __restrict__ win) {
   __shared__ hpx::DiskPrep s_dp[kTile];
   __shared__ double s_rel[kTile];
   __shared__ double s_lo[kRangeWaves][kRangeThreads], s_hi[kRangeWaves][kRangeThreads];
   __shared__ int s_fl[kRangeWaves][kRangeThreads];
-  __shared__ uint32_t s_wsum[kRangeWaves];
-  __shared__ uint64_t s_wcnt[kRangeWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t off = range_off[tile];
   const int64_t nring = (int64_t)((range_off[tile + 1] - off) / 2);
@@ -307,10 +292,7 @@ __device__ __forceinline__ void tile_ranges_body(
   }
   __syncthreads();
   const int64_t f = ring_first[tile];
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   constexpr int kPer = kTile / kRangeWaves;
-  uint32_t written = 0;
-  uint64_t total = 0;
   for (int64_t q0 = 0; q0 < nring; q0 += kRangeThreads) {
     const int nb = (int)((nring - q0) < kRangeThreads ? (nring - q0) : kRangeThreads);
     // partial unions: wavefront `wave` covers targets [wave*kPer, (wave+1)*kPer)
@@ -335,9 +317,9 @@ __device__ __forceinline__ void tile_ranges_body(
       s_fl[wave][q] = fl;
     }
     __syncthreads();
-    uint32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
     if (tid < nb) {
-      const int64_t i = f + q0 + tid;
+      const int64_t q = q0 + tid;
+      const int64_t i = f + q;
       double lo = 1e300, hi = -1e300;
       int fl = 0;
 #pragma unroll
@@ -347,75 +329,110 @@ __device__ __forceinline__ void tile_ranges_body(
         fl |= s_fl[w][tid];
       }
       const int full = (fl & 2) || ((fl & 1) && hi - lo >= hpx::kTwoPi);
-      if (fl) {
-        int64_t plo[2], phi[2];
-        const int nr = hpx::ring_window_ranges(nside, i, cphi + lo, cphi + hi, full, plo, phi);
-        const uint32_t rb = ring_off[i], re = ring_off[i + 1];
-        if (re > rb) {
-          b0 = lower_bound_u32(keys, rb, re, (uint64_t)plo[0]);
-          e0 = lower_bound_u32(keys, b0, re, (uint64_t)phi[0] + 1);
-          if (nr >= 2) {
-            b1 = lower_bound_u32(keys, rb, re, (uint64_t)plo[1]);
-            e1 = lower_bound_u32(keys, b1, re, (uint64_t)phi[1] + 1);
-          }
-        }
-      }
-    }
-    const bool h0 = e0 > b0, h1 = e1 > b1;
-    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
-    const uint32_t wcount = (uint32_t)(__popcll(m0) + __popcll(m1));
-    const double wc = wave_sum((double)((h0 ? e0 - b0 : 0u) + (h1 ? e1 - b1 : 0u)));
-    if (lane == 0) {
-      s_wsum[wave] = wcount;
-      s_wcnt[wave] = (uint64_t)wc;
-    }
-    __syncthreads();
-    uint32_t base = written;
-    for (int w = 0; w < wave; ++w) base += s_wsum[w];
-    uint32_t k = base + (uint32_t)(__popcll(m0 & lt) + __popcll(m1 & lt));
-    if (h0) {
-      ranges[2 * (off + k) + 0] = b0;
-      ranges[2 * (off + k) + 1] = e0 - b0;
-      ++k;
-    }
-    if (h1) {
-      ranges[2 * (off + k) + 0] = b1;
-      ranges[2 * (off + k) + 1] = e1 - b1;
-    }
-    for (int w = 0; w < kRangeWaves; ++w) {
-      written += s_wsum[w];
-      total += s_wcnt[w];
+      int64_t plo[2] = {1, 1}, phi[2] = {0, 0};
+      if (fl) hpx::ring_window_ranges(nside, i, cphi + lo, cphi + hi, full, plo, phi);
+      uint32_t* wq = win + 2 * (off + 2 * q);
+      wq[0] = (uint32_t)plo[0];
+      wq[1] = (uint32_t)phi[0];
+      wq[2] = (uint32_t)plo[1];
+      wq[3] = (uint32_t)phi[1];
     }
     __syncthreads();
   }
-  if (tid == 0) {
+}
+
+__global__ void __launch_bounds__(kRangeThreads) k_tile_windows(
+    const double* __restrict__ caps, const double* __restrict__ txyz, int64_t nslots,
+    int64_t nside, double rho, const int32_t* __restrict__ ring_first,
+    const uint64_t* __restrict__ range_off, uint32_t* __restrict__ win) {
+  tile_windows_body(blockIdx.x, caps, txyz, nslots, nside, rho, ring_first, range_off, win);
+}
+
+hipError_t launch_tile_windows(const double* caps, const double* txyz, int64_t nslots,
+                               int64_t ntiles, int64_t nside, double rho,
+                               const int32_t* ring_first, const uint64_t* range_off,
+                               uint32_t* win, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_windows, dim3((unsigned)ntiles), dim3(kRangeThreads), 0, st, caps,
+                     txyz, nslots, nside, rho, ring_first, range_off, win);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Candidate ranges of a grid call: one wavefront per tile, one window slot
+// per lane.  Two binary searches in the ring's sorted segment turn a pixel
+// range into a range of sorted samples; the non-empty ones are compacted in
+// slot (ring) order.
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, uint32_t lo,
+                                                    uint32_t hi, uint64_t v) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((uint64_t)keys[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void tile_ranges_body(
+    int64_t tile, const int32_t* __restrict__ ring_first, const uint64_t* __restrict__ range_off,
+    const uint32_t* __restrict__ win, const uint32_t* __restrict__ keys,
+    const uint32_t* __restrict__ ring_off, uint32_t* __restrict__ ranges,
+    uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
+  const int lane = threadIdx.x;
+  const uint64_t off = range_off[tile];
+  const int64_t ns = (int64_t)(range_off[tile + 1] - off);
+  const int64_t f = ring_first[tile];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t written = 0;
+  uint64_t total = 0;
+  for (int64_t s0 = 0; s0 < ns; s0 += 64) {
+    const int64_t s = s0 + lane;
+    uint32_t b = 0, e = 0;
+    if (s < ns) {
+      const uint32_t lo = win[2 * (off + s)], hi = win[2 * (off + s) + 1];
+      if (lo <= hi) {
+        const int64_t i = f + (s >> 1);
+        const uint32_t rb = ring_off[i], re = ring_off[i + 1];
+        b = lower_bound_u32(keys, rb, re, (uint64_t)lo);
+        e = lower_bound_u32(keys, b, re, (uint64_t)hi + 1);
+      }
+    }
+    const bool h = e > b;
+    const uint64_t m = __ballot(h);
+    const uint32_t k = written + (uint32_t)__popcll(m & lt);
+    if (h) {
+      ranges[2 * (off + k) + 0] = b;
+      ranges[2 * (off + k) + 1] = e - b;
+    }
+    written += (uint32_t)__popcll(m);
+    total += (uint64_t)wave_sum((double)(e - b));
+  }
+  if (lane == 0) {
     nranges[tile] = written;
     ncand[tile] = total;
   }
 }
 
-__global__ void __launch_bounds__(kRangeThreads) k_tile_ranges(
-    const double* __restrict__ caps, const double* __restrict__ txyz, int64_t nslots,
-    int64_t nside, double rho, const int32_t* __restrict__ ring_first,
-    const uint64_t* __restrict__ range_off, const uint32_t* __restrict__ keys,
+__global__ void __launch_bounds__(64) k_tile_ranges(
+    const int32_t* __restrict__ ring_first, const uint64_t* __restrict__ range_off,
+    const uint32_t* __restrict__ win, const uint32_t* __restrict__ keys,
     const uint32_t* __restrict__ ring_off, uint32_t* __restrict__ ranges,
     uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
-  tile_ranges_body(blockIdx.x, caps, txyz, nslots, nside, rho, ring_first, range_off, keys,
-                   ring_off, ranges, nranges, ncand);
+  tile_ranges_body(blockIdx.x, ring_first, range_off, win, keys, ring_off, ranges, nranges, ncand);
 }
 
-// Batches: one block per tile of any job; the job's own tables, nside and
-// radius, its range slots at rbase and its ring offsets at ro_off.
-__global__ void __launch_bounds__(kRangeThreads) k_batch_tile_ranges(
+// Batches: one wavefront per tile of any job; the job's own window slots,
+// its range slots at rbase and its ring offsets at ro_off.
+__global__ void __launch_bounds__(64) k_batch_tile_ranges(
     const BatchJob* __restrict__ jobs, const int64_t* __restrict__ toff, int njobs,
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ring_off,
     uint32_t* __restrict__ ranges, uint32_t* __restrict__ nranges, uint64_t* __restrict__ ncand) {
   const int64_t g = blockIdx.x;
   const int j = job_of(toff, njobs, g);
   const BatchJob& jb = jobs[j];
-  tile_ranges_body(g - jb.toff, jb.caps, jb.txyz, jb.nslots, jb.nside, jb.rho, jb.ring_first,
-                   jb.range_off, keys, ring_off + jb.ro_off, ranges + 2 * jb.rbase,
-                   nranges + jb.toff, ncand + jb.toff);
+  tile_ranges_body(g - jb.toff, jb.ring_first, jb.range_off, jb.win, keys, ring_off + jb.ro_off,
+                   ranges + 2 * jb.rbase, nranges + jb.toff, ncand + jb.toff);
 }
 
 hipError_t launch_batch_tile_ranges(const BatchJob* jobs, const int64_t* toff, int njobs,
@@ -423,20 +440,18 @@ hipError_t launch_batch_tile_ranges(const BatchJob* jobs, const int64_t* toff, i
                                     uint32_t* ranges, uint32_t* nranges, uint64_t* ncand,
                                     hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_tile_ranges, dim3((unsigned)ntiles), dim3(kRangeThreads), 0, st, jobs,
-                     toff, njobs, keys, ring_off, ranges, nranges, ncand);
+  hipLaunchKernelGGL(k_batch_tile_ranges, dim3((unsigned)ntiles), dim3(64), 0, st, jobs, toff,
+                     njobs, keys, ring_off, ranges, nranges, ncand);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const double* caps, const double* txyz, int64_t nslots,
-                              int64_t ntiles, int64_t nside, double rho,
-                              const int32_t* ring_first, const uint64_t* range_off,
+hipError_t launch_tile_ranges(int64_t ntiles, const int32_t* ring_first,
+                              const uint64_t* range_off, const uint32_t* win,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ntiles), dim3(kRangeThreads), 0, st, caps,
-                     txyz, nslots,
-                     nside, rho, ring_first, range_off, keys, ring_off, ranges, nranges, ncand);
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ntiles), dim3(64), 0, st, ring_first, range_off,
+                     win, keys, ring_off, ranges, nranges, ncand);
   return hipGetLastError();
 }
 
