@@ -250,7 +250,7 @@ def run_cube(a, dev):
                               "kernel_ms": round(kms32, 4)}
         extra["speedup_vs_fp32"] = round(ms32 / ms, 3)
         log(f"fp32: {ms32:.3f} ms/step, kernel {kms32:.3f} ms")
-    alg_bytes = wl.nsamples * (wl.nchan * data.element_size() + 24) + ntarget * (wl.nchan * 4 + 4)
+    alg_bytes = wl.nsamples * (wl.nchan * data.element_size() + 16) + ntarget * (wl.nchan * 4 + 4)
     if headline == "fp32":
         roof = roof_alu(2.0 * contributions + FLOPS_PER_PAIR * pairs, kms, "contraction_fp32")
     else:
