@@ -74,6 +74,7 @@ cg::TileView tile_view(const cg_gridder* g) {
   tv.nslots = g->nslots;
   tv.ncap = g->ncap;
   tv.ntiles = g->ntiles;
+  tv.ntx = g->kind == 0 ? g->ntx : 0;
   return tv;
 }
 

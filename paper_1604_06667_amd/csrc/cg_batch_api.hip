@@ -195,6 +195,7 @@ cg_status upload_tables(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
     q.toff = b->toff[(size_t)j];
     q.ntiles = g->ntiles;
     q.nslots = g->nslots;
+    q.ntx = g->kind == 0 ? g->ntx : 0;
     q.rbase = b->rbase[(size_t)j];
     q.ntarget = g->ntarget;
     q.txyz = g->txyz.as<double>();

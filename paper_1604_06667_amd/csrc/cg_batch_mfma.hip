@@ -45,6 +45,7 @@ __global__ void __launch_bounds__(kBatchWaves * 64) k_batch_mfma(
     tv.nslots = jb.nslots;
     tv.ncap = ncap;
     tv.ntiles = jb.ntiles;
+    tv.ntx = jb.ntx;   // same candidate order as the per-grid kernel
     OutView ov;
     ov.S = nullptr;
     ov.W = nullptr;

@@ -36,6 +36,7 @@ struct TileView {
   int64_t nslots;
   int64_t ncap;                // stride of cxyz
   int64_t ntiles;
+  int64_t ntx;                 // tiles per row of a WCS grid (0: sight lines)
 };
 
 // Block -> tile map that keeps consecutive tiles on one XCD: workgroups are
@@ -57,6 +58,18 @@ __device__ __forceinline__ void work_of_block(int64_t b, int64_t ntiles, int64_t
   const int64_t v = tile_of_block(b, ntiles * npass);
   *tile = v / npass;
   *pass = v % npass;
+}
+// Visit order of the tiles of a WCS grid (ntx tiles per row): strips of
+// kStrip tile rows, each walked column by column, so that the tiles running
+// together on one XCD form a compact block that shares candidate samples
+// both across and along the columns.  v is the position in the visit order.
+constexpr int64_t kStrip = 4;
+__device__ __forceinline__ int64_t strip_tile(int64_t v, int64_t ntiles, int64_t ntx) {
+  const int64_t nty = ntiles / ntx;
+  const int64_t s = v / (kStrip * ntx);
+  const int64_t h = (nty - s * kStrip) < kStrip ? (nty - s * kStrip) : kStrip;
+  const int64_t w = v - s * kStrip * ntx;
+  return (s * kStrip + w % h) * ntx + w / h;
 }
 
 // ---------------------------------------------------------------- device math
@@ -187,6 +200,7 @@ struct BatchJob {
   int64_t ld, nchan, nside;
   int64_t ro_off;              // offset of the ring offsets [4 nside + 1]
   int64_t toff, ntiles, nslots;  // first global tile; tiles; target slots
+  int64_t ntx;                 // tiles per row (WCS grids), 0 for sight lines
   int64_t rbase;               // offset (in ranges) of the job's range slots
   int64_t ntarget;
   const double* txyz;

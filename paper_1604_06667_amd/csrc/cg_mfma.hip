@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
   constexpr int CP = NW * BPW * 32;
   int64_t tile, pass;
   work_of_block(blockIdx.x, tv.ntiles, (nchan + CP - 1) / CP, &tile, &pass);
+  if (tv.ntx > 0) tile = strip_tile(tile, tv.ntiles, tv.ntx);
   const int64_t c0 = pass * CP;
   const int64_t cend = c0 + CP < nchan ? c0 + CP : nchan;
   mfma_tile<NW, BPW, KT, MODE, FULL, T>(tv, kp, data, zrow, ld, nchan, ov, tile, c0, cend);

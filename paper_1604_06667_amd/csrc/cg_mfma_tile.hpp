@@ -191,9 +191,14 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   const int64_t zoff = (int64_t)(zrow - data) - c0;   // offset that lands on the zero row
   double rx = nan, ry = nan, rz = nan;
   int64_t rrow = zoff;
+  // Odd tile rows of a WCS grid walk their candidates backwards (bottom ring
+  // first): a tile and the one below it then reach the rings they share at
+  // the same time, while those samples are in L2.
+  const bool rev = tv.ntx > 0 && ((tile / tv.ntx) & 1);
   auto load_rec = [&](int64_t ch) {
-    const uint64_t q = cb0 + (uint64_t)ch * MK + t;
-    if (ch < nchunks && q < cb1) {
+    const uint64_t idx = (uint64_t)ch * MK + t;
+    const uint64_t q = rev ? cb1 - 1 - idx : cb0 + idx;
+    if (ch < nchunks && idx < cb1 - cb0) {
       rx = tv.cxyz[q];
       ry = tv.cxyz[cap + q];
       rz = tv.cxyz[2 * cap + q];
