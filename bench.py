@@ -323,8 +323,11 @@ def run_sightlines(a, dev):
     g.set_precision("bf16")
     pairs, contributions = count_contributions(g, lon, lat, wl.nchan)
     nt = wl.ntargets()
-    cube = torch.empty((wl.nchan, nt), dtype=torch.float32, device=dev)
     weights = torch.empty((nt,), dtype=torch.float32, device=dev)
+    # one spectrum per sight line contiguous ([T][C]); the channel-major
+    # ([C][T]) cube is timed beside it for BF16
+    g.set_output_layout("target")
+    cube = torch.empty((nt, wl.nchan), dtype=torch.float32, device=dev)
     res, cubes = {}, {}
     for prec in ["bf16", "fp16", "fp32"]:
         if prec == "fp32" and a.no_compare:
@@ -333,14 +336,22 @@ def run_sightlines(a, dev):
         st = a.steps if prec != "fp32" else max(2, a.steps // 2)
         ms, kms, nl = time_path(g, lon, lat, data, cube, weights, st, 1 if prec == "fp32" else a.warmup)
         res[prec] = (ms, kms)
-        cubes[prec] = cube.clone()
+        cubes[prec] = cube.t().contiguous()
         log(f"{prec}: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
+    g.set_precision("bf16")
+    g.set_output_layout("channel")
+    cube_c = torch.empty((wl.nchan, nt), dtype=torch.float32, device=dev)
+    ms_c, kms_c, _ = time_path(g, lon, lat, data, cube_c, weights, a.steps, a.warmup)
+    log(f"bf16 channel-major cube: {ms_c:.3f} ms/step, contraction kernel {kms_c:.3f} ms")
+    del cube_c
     ms, kms = res["bf16"]
     alg_bytes = (wl.nsamples * (wl.nchan * data.element_size() + 16) + nt * 16 +
                  nt * (wl.nchan * 4 + 4))
     roof = roof_hbm(alg_bytes, kms, "contraction_sightlines_bf16")
     extra = {"paths": {p: {"value": contributions / (m / 1e3), "ms_per_step": round(m, 4),
                            "kernel_ms": round(k, 4)} for p, (m, k) in res.items()}}
+    extra["bf16_channel_major"] = {"value": contributions / (ms_c / 1e3),
+                                   "ms_per_step": round(ms_c, 4), "kernel_ms": round(kms_c, 4)}
     if "fp32" in res:
         extra["speedup_vs_fp32"] = round(res["fp32"][0] / ms, 3)
     cpu = None
@@ -355,7 +366,7 @@ def run_sightlines(a, dev):
                     contributions / (ms / 1e3), ms, "bf16",
                     {"samples": wl.nsamples, "targets": nt, "channels": wl.nchan,
                      "nside": g.nside, "pairs": pairs, "contributions": contributions,
-                     "contraction": "bf16"}, roof, cpu)
+                     "contraction": "bf16", "layout": "target-major [T][C]"}, roof, cpu)
     out.update(extra)
     return out
 

@@ -73,6 +73,14 @@ typedef enum cg_prec {
                          data must lie within the FP16 range */
 } cg_prec;
 
+/* memory layout of the cubes a handle writes (cg_get_datacube,
+ * cg_grid_datacube, batches) */
+typedef enum cg_layout {
+  CG_LAYOUT_CHANNEL_MAJOR = 0,  /* [nchan][naxis2][naxis1] or [nchan][ntarget] (FITS order) */
+  CG_LAYOUT_TARGET_MAJOR = 1    /* [naxis2][naxis1][nchan] or [ntarget][nchan]: one spectrum per
+                                   target contiguous (sight-line lists, spectral analysis) */
+} cg_layout;
+
 typedef enum cg_kernel_type {
   CG_GAUSS1D = 0,  /* params = {sigma}: w = exp(-d^2 / (2 sigma^2))            (Listing 1) */
   CG_GAUSS2D = 1   /* params = {sigma_maj, sigma_min, pa}: elliptical Gaussian in world
@@ -133,6 +141,12 @@ cg_status cg_set_nside(cg_gridder* g, int64_t nside);
  * Errors: CG_E_INVALID. */
 cg_status cg_set_precision(cg_gridder* g, int32_t prec);
 
+/* Select the layout of the cubes this handle writes (cg_layout).  Default
+ * CG_LAYOUT_CHANNEL_MAJOR, the order of get_datacube in Listing 1 (Sect.
+ * 3.5); the weight map is [naxis2][naxis1] / [ntarget] in both.  Errors:
+ * CG_E_INVALID. */
+cg_status cg_set_output_layout(cg_gridder* g, int32_t layout);
+
 /* grid(lon, lat, signal) (Listing 1; Sect. 2.1 Eq. 1-2): add the
  * contributions of `nsamples` samples to S and W.  lon_deg, lat_deg: device
  * FP64 [nsamples].  data: device, `dtype` elements, row n at data + n*ld_data
@@ -181,7 +195,7 @@ cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double*
                              int64_t nsamples, int32_t* counts, uint64_t* hashes, void* stream);
 
 /* Handle queries (host):  what = 0 ntargets, 1 nchan, 2 nside, 3 ntiles,
- * 4 candidates in the last grid call, 5 precision, 6 device. */
+ * 4 candidates in the last grid call, 5 precision, 6 device, 7 layout. */
 cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value);
 
 /* Measurement: while enabled, every launch of the contraction kernel (the

@@ -18,6 +18,7 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 KERNEL = {"gauss1d": 0, "gauss2d": 1}
 PROJ = {"CAR": 0, "SIN": 1}
+LAYOUT = {"channel": 0, "target": 1}
 
 
 class CgError(RuntimeError):
@@ -49,6 +50,7 @@ SIGNATURES = {
     "cg_set_kernel": (_i32, [_vp, _i32, _P(_d), _i32, _d, _d]),
     "cg_set_nside": (_i32, [_vp, _i64]),
     "cg_set_precision": (_i32, [_vp, _i32]),
+    "cg_set_output_layout": (_i32, [_vp, _i32]),
     "cg_grid": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp]),
     "cg_get_datacube": (_i32, [_vp, _vp, _vp]),
     "cg_get_weights": (_i32, [_vp, _vp, _vp]),
@@ -211,6 +213,13 @@ class _Gridder:
             raise CgError(E_INVALID, f"unknown precision {prec!r}")
         check(lib().cg_set_precision(self._handle(), PREC[prec]))
 
+    def set_output_layout(self, layout):
+        """'channel' ([C][...], default) or 'target' ([...][C]) cubes."""
+        if layout not in LAYOUT:
+            raise CgError(E_INVALID, f"unknown layout {layout!r}")
+        check(lib().cg_set_output_layout(self._handle(), LAYOUT[layout]))
+        self.layout = layout
+
     def _coords(self, lon, lat):
         torch = _torch()
         if lon.shape != lat.shape or lon.dim() != 1:
@@ -226,7 +235,12 @@ class _Gridder:
 
     def _empty_out(self, nch):
         torch = _torch()
-        shape = (nch,) + self.out_shape if nch else self.out_shape
+        if not nch:
+            shape = self.out_shape
+        elif getattr(self, "layout", "channel") == "target":
+            shape = self.out_shape + (nch,)
+        else:
+            shape = (nch,) + self.out_shape
         return torch.empty(shape, dtype=torch.float32, device=f"cuda:{self.device}")
 
     # Listing 1: get_datacube()

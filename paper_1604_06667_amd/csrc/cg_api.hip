@@ -289,6 +289,14 @@ cg_status cg_set_nside(cg_gridder* g, int64_t nside) {
   return CG_OK;
 }
 
+cg_status cg_set_output_layout(cg_gridder* g, int32_t layout) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (layout != CG_LAYOUT_CHANNEL_MAJOR && layout != CG_LAYOUT_TARGET_MAJOR)
+    return fail(CG_E_INVALID, "unknown layout %d", layout);
+  g->layout = layout;
+  return CG_OK;
+}
+
 cg_status cg_set_precision(cg_gridder* g, int32_t prec) {
   if (!g) return fail(CG_E_INVALID, "null handle");
   if (prec < CG_PREC_FP32 || prec > CG_PREC_FP16) return fail(CG_E_INVALID, "unknown precision %d", prec);
@@ -338,6 +346,7 @@ cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* l
   cg::OutView ov{};
   ov.cube = cube_out;
   ov.wout = weights_out;
+  cube_strides(g, &ov.cst, &ov.tst);
   ov.slot_target = g->slot_target.as<int32_t>();
   ov.ntarget = g->ntarget;
   ov.mode = cg::ACC_FINAL;
@@ -354,9 +363,11 @@ cg_status cg_get_datacube(cg_gridder* g, float* out, void* stream) {
     CG_HIP(cg::launch_fill(out, g->nchan * g->ntarget, __builtin_nanf(""), st), "fill");
     return CG_OK;
   }
+  int64_t cst, tst;
+  cube_strides(g, &cst, &tst);
   CG_HIP(cg::launch_normalize(g->S.as<float>(), g->W.as<double>(), g->Wn.as<double>(),
-                              g->target_slot.as<int32_t>(), g->nslots, g->nchan, g->ntarget, out,
-                              nullptr, st),
+                              g->target_slot.as<int32_t>(), g->nslots, g->nchan, g->ntarget, cst,
+                              tst, out, nullptr, st),
          "normalize");
   return CG_OK;
 }
@@ -372,7 +383,7 @@ cg_status cg_get_weights(cg_gridder* g, float* out, void* stream) {
     return CG_OK;
   }
   CG_HIP(cg::launch_normalize(nullptr, g->W.as<double>(), g->Wn.as<double>(),
-                              g->target_slot.as<int32_t>(), g->nslots, g->nchan, g->ntarget,
+                              g->target_slot.as<int32_t>(), g->nslots, g->nchan, g->ntarget, 0, 1,
                               nullptr, out, st),
          "weights");
   return CG_OK;
@@ -434,6 +445,7 @@ cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value) {
     case 4: *value = g->last_ncand; break;
     case 5: *value = g->prec; break;
     case 6: *value = g->device; break;
+    case 7: *value = g->layout; break;
     default: return fail(CG_E_INVALID, "unknown query %d", what);
   }
   return CG_OK;

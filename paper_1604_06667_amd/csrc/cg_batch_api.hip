@@ -206,6 +206,7 @@ cg_status upload_tables(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
     q.win = g->win.as<uint32_t>();
     q.slot_target = g->slot_target.as<int32_t>();
     q.cube = in[j].cube_out;
+    cube_strides(g, &q.cst, &q.tst);
     q.wout = in[j].weights_out;
     q.kp = g->kp;
     q.rho = g->support_rad + 1e-9;

@@ -54,6 +54,8 @@ __global__ void __launch_bounds__(kBatchWaves * 64) k_batch_mfma(
     ov.wout = jb.wout;
     ov.slot_target = jb.slot_target;
     ov.ntarget = jb.ntarget;
+    ov.cst = jb.cst;
+    ov.tst = jb.tst;
     ov.mode = ACC_FINAL;
     mfma_tile<kBatchWaves, BPW, 2, MODE, false, T>(tv, jb.kp, (const T*)jb.data, zrow, jb.ld,
                                                    jb.nchan, ov, item.tile, item.c0, item.cend);

@@ -102,7 +102,8 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
     const int32_t t = ov.slot_target[slot];
     if (t >= 0) {
       for (int c = 0; c < CMAX && c < nchan; ++c)
-        ov.cube[(int64_t)c * ov.ntarget + t] = wacc > 0.0 ? (float)(acc[c] / wacc) : qnan_f();
+        ov.cube[(int64_t)c * ov.cst + (int64_t)t * ov.tst] =
+            wacc > 0.0 ? (float)(acc[c] / wacc) : qnan_f();
       if (ov.wout) ov.wout[t] = (float)wacc;
     }
   } else {
@@ -277,15 +278,18 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
     }
   }
   __syncthreads();
+  // consecutive threads write consecutive targets of a channel, or (target-
+  // major cubes) consecutive channels of a target
+  const bool tmaj = fin && ov.tst != 1;
   for (int idx = t; idx < CB * kTile; idx += 64 * NWV) {
-    const int c = idx / kTile;
-    const int l = idx % kTile;
+    const int c = tmaj ? idx % CB : idx / kTile;
+    const int l = tmaj ? idx / CB : idx % kTile;
     if (c0 + c >= nchan) continue;
     const int64_t slot = tile * kTile + l;
     const float o = s_d[c * kTile + l];
     if (fin) {
       const int32_t tg = ov.slot_target[slot];
-      if (tg >= 0) ov.cube[(c0 + c) * ov.ntarget + tg] = o;
+      if (tg >= 0) ov.cube[(c0 + c) * ov.cst + (int64_t)tg * ov.tst] = o;
     } else if (ov.mode == ACC_ADD) {
       ov.S[(c0 + c) * ns + slot] += o;
     } else {
@@ -418,6 +422,7 @@ __global__ void __launch_bounds__(256) k_normalize(const float* __restrict__ S,
                                                    const double* __restrict__ Wn,
                                                    const int32_t* __restrict__ target_slot,
                                                    int64_t nslots, int64_t nchan, int64_t ntarget,
+                                                   int64_t cst, int64_t tst,
                                                    float* __restrict__ cube, float* __restrict__ wout) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntarget) return;
@@ -425,18 +430,19 @@ __global__ void __launch_bounds__(256) k_normalize(const float* __restrict__ S,
   const int64_t s = target_slot[t];
   if (cube) {
     const double wn = Wn[s];
-    cube[c * ntarget + t] = wn > 0.0 ? (float)((double)S[c * nslots + s] / wn) : qnan_f();
+    cube[c * cst + t * tst] = wn > 0.0 ? (float)((double)S[c * nslots + s] / wn) : qnan_f();
   }
   if (wout && c == 0) wout[t] = (float)W[s];
 }
 
 hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
                             const int32_t* target_slot, int64_t nslots, int64_t nchan,
-                            int64_t ntarget, float* cube, float* wout, hipStream_t st) {
+                            int64_t ntarget, int64_t cst, int64_t tst, float* cube, float* wout,
+                            hipStream_t st) {
   if (ntarget <= 0) return hipSuccess;
   const int64_t gy = cube ? nchan : 1;
   hipLaunchKernelGGL(k_normalize, dim3((unsigned)((ntarget + 255) / 256), (unsigned)gy), dim3(256),
-                     0, st, S, W, Wn, target_slot, nslots, nchan, ntarget, cube, wout);
+                     0, st, S, W, Wn, target_slot, nslots, nchan, ntarget, cst, tst, cube, wout);
   return hipGetLastError();
 }
 

@@ -91,6 +91,7 @@ struct cg_gridder {
   int64_t nside = 0;
   bool nside_fixed = false;
   int prec = CG_PREC_FP32;
+  int layout = CG_LAYOUT_CHANNEL_MAJOR;   // of the cubes written by this handle
   bool span_valid = false;
   cgh::DevBuf ring_first, span_bound, range_off, win;
   int64_t total_ranges = 0;
@@ -170,4 +171,14 @@ inline cg_status ensure_span(cg_gridder* g, hipStream_t st) {
   return CG_OK;
 }
 
+// element strides (channel, target) of a cube in the handle's layout
+inline void cube_strides(const cg_gridder* g, int64_t* cst, int64_t* tst) {
+  if (g->layout == CG_LAYOUT_TARGET_MAJOR) {
+    *cst = 1;
+    *tst = g->nchan;
+  } else {
+    *cst = g->ntarget;
+    *tst = 1;
+  }
+}
 }  // namespace cgh

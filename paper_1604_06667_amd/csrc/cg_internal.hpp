@@ -178,6 +178,7 @@ struct OutView {
   float* wout;         // ACC_FINAL: weights in user layout (may be null)
   const int32_t* slot_target;
   int64_t ntarget;
+  int64_t cst, tst;    // element strides of the cube: channel, target (layout)
   int mode;
 };
 hipError_t launch_gather_fp32(const TileView& tv, const KernelParams& kp, const void* data,
@@ -210,8 +211,9 @@ struct BatchJob {
   const uint64_t* range_off;   // [ntiles + 1] job-local range-slot offsets
   const uint32_t* win;         // pixel windows of the range slots
   const int32_t* slot_target;
-  float* cube;                 // [nchan][ntarget] normalised output
+  float* cube;                 // normalised output (strides cst per channel, tst per target)
   float* wout;                 // [ntarget] weight map (may be null)
+  int64_t cst, tst;
   KernelParams kp;
   double rho;                  // support radius + margin (rad)
 };
@@ -271,7 +273,8 @@ hipError_t launch_stats(const TileView& tv, const KernelParams& kp, const int32_
                         int32_t* counts, uint64_t* hashes, hipStream_t st);
 hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
                             const int32_t* target_slot, int64_t nslots, int64_t nchan,
-                            int64_t ntarget, float* cube, float* wout, hipStream_t st);
+                            int64_t ntarget, int64_t cst, int64_t tst, float* cube, float* wout,
+                            hipStream_t st);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
 
 }  // namespace cg

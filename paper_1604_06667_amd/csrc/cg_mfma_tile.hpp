@@ -363,7 +363,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
         const double wr = s_wfin[1][n];
         const float inv = wr > 0.0 ? (float)(1.0 / wr) : 0.0f;
         const bool filled = wr > 0.0;
-        float* __restrict__ dst = ov.cube + tg;
+        float* __restrict__ dst = ov.cube + (int64_t)tg * ov.tst;
 #pragma unroll
         for (int b = 0; b < BPW; ++b) {
 #pragma unroll
@@ -371,7 +371,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
             const int m = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
             const int64_t c = c0 + (wv * BPW + b) * 32 + m;
             if (!FULL && c >= cend) continue;
-            dst[c * ov.ntarget] = filled ? acc[b][nb][j] * inv : __int_as_float(0x7fc00000);
+            dst[c * ov.cst] = filled ? acc[b][nb][j] * inv : __int_as_float(0x7fc00000);
           }
         }
       }
