@@ -394,7 +394,7 @@ __device__ __forceinline__ float to_f32<uint16_t>(const uint16_t* p, int64_t i) 
 template <>
 __device__ __forceinline__ float to_f32<_Float16>(const _Float16* p, int64_t i) { return (float)p[i]; }
 
-template <typename T>
+template <typename T, bool VEC4>
 __global__ void __launch_bounds__(256) k_permute(const uint32_t* __restrict__ vals,
                                                  const uint32_t* __restrict__ nvalid_p,
                                                  const double* __restrict__ lon,
@@ -415,7 +415,15 @@ __global__ void __launch_bounds__(256) k_permute(const uint32_t* __restrict__ va
   sx[cap + p] = cd * sa;
   sx[2 * cap + p] = sd;
   if (with_data) {
-    for (int64_t c = 0; c < nchan; ++c) sdata[p * nchan + c] = to_f32<T>(data, src * ld + c);
+    if constexpr (VEC4) {
+      // FP32 rows with nchan and ld multiples of 4 and 16-byte aligned: whole
+      // 16-byte pieces per load and store
+      const float4* in = reinterpret_cast<const float4*>(data + src * ld);
+      float4* out = reinterpret_cast<float4*>(sdata + p * nchan);
+      for (int64_t c = 0; c < nchan / 4; ++c) out[c] = in[c];
+    } else {
+      for (int64_t c = 0; c < nchan; ++c) sdata[p * nchan + c] = to_f32<T>(data, src * ld + c);
+    }
   }
 }
 
@@ -430,19 +438,23 @@ hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int6
   const int wd = with_data ? 1 : 0;
   switch (dtype) {
     case 0:
-      hipLaunchKernelGGL(k_permute<double>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+      hipLaunchKernelGGL((k_permute<double, false>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
                          (const double*)data, ld, nchan, wd, cap, sx, sdata);
       break;
     case 1:
-      hipLaunchKernelGGL(k_permute<float>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
-                         (const float*)data, ld, nchan, wd, cap, sx, sdata);
+      if (wd && nchan % 4 == 0 && ld % 4 == 0 && ((uintptr_t)data & 15) == 0)
+        hipLaunchKernelGGL((k_permute<float, true>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+                           (const float*)data, ld, nchan, wd, cap, sx, sdata);
+      else
+        hipLaunchKernelGGL((k_permute<float, false>), grid, blk, 0, st, vals, nvalid_dev, lon,
+                           lat, (const float*)data, ld, nchan, wd, cap, sx, sdata);
       break;
     case 2:
-      hipLaunchKernelGGL(k_permute<_Float16>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+      hipLaunchKernelGGL((k_permute<_Float16, false>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
                          (const _Float16*)data, ld, nchan, wd, cap, sx, sdata);
       break;
     default:
-      hipLaunchKernelGGL(k_permute<uint16_t>, grid, blk, 0, st, vals, nvalid_dev, lon, lat,
+      hipLaunchKernelGGL((k_permute<uint16_t, false>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
                          (const uint16_t*)data, ld, nchan, wd, cap, sx, sdata);
       break;
   }
@@ -455,28 +467,39 @@ hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int6
 
 __global__ void __launch_bounds__(1024) k_scan_u64(const uint64_t* __restrict__ in,
                                                    uint64_t* __restrict__ out, int64_t n) {
+  // one workgroup walks the array in coalesced rounds of 1024 x 4 values,
+  // each round a block scan on top of the running total
   __shared__ uint64_t part[1024];
   const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = (int64_t)t * per;
-  const int64_t e = b + per < n ? b + per : n;
-  uint64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += in[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint64_t v = (t >= off) ? part[t - off] : 0ull;
+  uint64_t carry = 0;
+  for (int64_t r0 = 0; r0 < n; r0 += 4096) {
+    uint64_t v[4];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = r0 + 4 * (int64_t)t + k;
+      v[k] = i < n ? in[i] : 0ull;
+      s += v[k];
+    }
+    part[t] = s;
     __syncthreads();
-    part[t] += v;
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint64_t u = t >= off ? part[t - off] : 0ull;
+      __syncthreads();
+      part[t] += u;
+      __syncthreads();
+    }
+    uint64_t run = carry + part[t] - s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = r0 + 4 * (int64_t)t + k;
+      if (i < n) out[i] = run;
+      run += v[k];
+    }
+    carry += part[1023];
     __syncthreads();
   }
-  uint64_t run = part[t] - s;
-  for (int64_t i = b; i < e; ++i) {
-    const uint64_t v = in[i];
-    out[i] = run;
-    run += v;
-  }
-  if (t == 1023) out[n] = part[1023];
+  if (t == 0) out[n] = carry;
 }
 
 hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st) {
