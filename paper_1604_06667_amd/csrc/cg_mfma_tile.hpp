@@ -125,7 +125,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   __shared__ int64_t s_row[3][MK];   // element offset of each candidate's row from data
   __shared__ double s_red[2][NW][kTile];
   __shared__ double s_wfin[2][kTile];
-  __shared__ double s_tg[kTile][KT == 0 ? 3 : 9];   // target xyz (+ major, minor axis)
+  __shared__ double s_tg[kTile][3];                    // target unit vectors
+  __shared__ float s_ax[KT == 0 ? 1 : kTile][6];       // major, minor axis (elliptical)
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t ns = tv.nslots;
@@ -166,8 +167,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
       }
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        s_tg[t][3 + q] = a[q];
-        s_tg[t][6 + q] = b[q];
+        s_ax[t][q] = (float)a[q];
+        s_ax[t][3 + q] = (float)b[q];
       }
     }
   }
@@ -215,23 +216,31 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     s_row[buf][t] = rrow;
   };
   // weight of candidate k of the chunk in record buffer rb -> weight buffer wb
+  // Kernel value of a pair.  The support test is FP64 on the chord; the
+  // value itself only needs FP32 accuracy (it is rounded to 16-bit operand
+  // parts), so the distance series, the elliptical form and the exponential
+  // are evaluated in FP32, branch-free, and masked by the test.
+  const float k1f = (float)kp.k1, kmajf = (float)kp.kmaj, kminf = (float)kp.kmin;
   auto weight = [&](int rb, int wb, int k) {
     const double dx = s_c[rb][k][0] - s_tg[nw][0];
     const double dy = s_c[rb][k][1] - s_tg[nw][1];
     const double dz = s_c[rb][k][2] - s_tg[nw][2];
     const double c2 = dx * dx + dy * dy + dz * dz;
-    float w = 0.0f;
-    if (c2 <= kp.cs2) {
-      if constexpr (KT == 0) {
-        w = exp2_neg(chord2_to_d2(c2) * kp.k1);
-      } else {
-        if (ell)
-          w = pair_weight(kp, c2, dx, dy, dz, s_tg[nw][3], s_tg[nw][4], s_tg[nw][5],
-                          s_tg[nw][6], s_tg[nw][7], s_tg[nw][8]);
-        else
-          w = exp2_neg(chord2_to_d2(c2) * kp.k1);
+    const float c = (float)c2;
+    float d2 = c * (1.0f + c * (1.0f / 12.0f + c * (1.0f / 90.0f + c * (1.0f / 560.0f +
+                    c * (1.0f / 3150.0f + c * (1.0f / 16632.0f))))));
+    if (c2 > 0.1225) d2 = (float)chord2_to_d2_exact(c2);   // chords beyond ~20 deg
+    float x = d2 * k1f;
+    if constexpr (KT != 0) {
+      if (ell) {
+        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        const float u = fx * s_ax[nw][0] + fy * s_ax[nw][1] + fz * s_ax[nw][2];
+        const float v = fx * s_ax[nw][3] + fy * s_ax[nw][4] + fz * s_ax[nw][5];
+        const float uu = u * u, vv = v * v, uv = uu + vv;
+        x = uv > 0.0f ? d2 * (uu * kmajf + vv * kminf) * __builtin_amdgcn_rcpf(uv) : 0.0f;
       }
     }
+    const float w = c2 <= kp.cs2 ? __builtin_amdgcn_exp2f(-x) : 0.0f;
     const uint16_t whi = to_bits<F16>(w);
     float wr = from_bits<F16>(whi);
     s_wt[wb][0][nw * KP + k] = whi;
