@@ -426,7 +426,7 @@ def run_batched(a, dev):
     roof = roof_hbm(alg_bytes, kms, "contraction_batched_bf16")
     extra = {"eager": {"value": contributions / (ms_eager / 1e3), "ms_per_step": round(ms_eager, 4)},
              "tuned": {"rows_per_workgroup": b.query(5), "half_items": b.query(6),
-                       "workgroups_per_cu": b.query(7), "items": b.query(3)}}
+                       "workgroups_per_cu": b.query(7), "shape": b.query(9), "items": b.query(3)}}
     cpu = None
     if not a.no_cpu:
         # the largest job's central 48x48 targets

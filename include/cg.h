@@ -252,10 +252,10 @@ cg_status cg_batch_create(cg_batch** out, cg_gridder* const* jobs, int32_t njobs
 cg_status cg_batch_grid(cg_batch* b, const cg_batch_job* in, void* stream);
 
 /* Autotuner: runs one cg_batch_grid on `in`, then times each configuration
- * of the persistent launch (channels per item: 256 or 512 matrix rows per
- * workgroup, items of full or half width, one or all resident workgroups per
- * compute unit) `reps` times on the same lookup and keeps the fastest for
- * later calls.  The outputs hold a valid result afterwards.  Waits for the
+ * of the persistent launch (workgroup shape: 8 or 4 wavefronts with one or
+ * two 32-channel blocks each, i.e. 128-512 matrix rows; items of full or half
+ * width; one or all resident workgroups per compute unit) `reps` times on the
+ * same lookup and keeps the fastest for later calls.  The outputs hold a valid result afterwards.  Waits for the
  * device.  Errors as cg_batch_grid. */
 cg_status cg_batch_tune(cg_batch* b, const cg_batch_job* in, int32_t reps, void* stream);
 
@@ -280,8 +280,8 @@ cg_status cg_batch_sync(cg_batch* b, void* stream);
 
 /* Batch queries (host): what = 0 njobs, 1 samples of the last pass,
  * 2 tiles, 3 work items, 4 candidates of the last eager pass, 5 matrix rows
- * per workgroup (256 or 512), 6 half-width items (0/1), 7 workgroups per
- * compute unit, 8 graph captured (0/1). */
+ * per workgroup (128-512), 6 half-width items (0/1), 7 workgroups per
+ * compute unit, 8 graph captured (0/1), 9 workgroup shape (0-3). */
 cg_status cg_batch_query(const cg_batch* b, int32_t what, int64_t* value);
 
 /* Measurement as cg_profile_enable / cg_profile_read: events bracket the

@@ -35,8 +35,8 @@ struct cg_batch {
   int64_t nitems = 0;
   bool items_valid = false;
   std::vector<int64_t> items_for_n;          // sample counts the queue was ordered for
-  // tuned launch shape
-  int bpw = 2, split = 0, bpc = 0;
+  // tuned launch shape (cg::launch_batch_mfma), item width, workgroups per CU
+  int shape = 1, split = 0, bpc = 0;
   // graph
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -115,7 +115,7 @@ double item_cost(const cg_gridder* g, int64_t n, int64_t cw) {
 // items of every job, jobs in order of decreasing estimated item cost.
 cg_status build_items(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
   const int njobs = (int)b->jobs.size();
-  const int64_t cp = 256 * (int64_t)b->bpw;
+  const int64_t cp = cg::batch_shape_rows(b->shape);
   struct JobOrder { int j; int64_t cw, npass; double cost; };
   std::vector<JobOrder> ord;
   int64_t total = 0;
@@ -295,7 +295,7 @@ cg_status contract_part(cg_batch* b, hipStream_t st, bool events) {
   CG_HIP(cg::launch_batch_mfma(dj, b->items.as<cg::BatchItem>(), b->nitems, b->counter.as<int>(),
                                b->cand_off.as<uint64_t>(), b->cand.as<uint32_t>(),
                                b->crow.as<uint32_t>(), b->cxyz.as<double>(), b->ncap, b->zrow.p,
-                               b->dtype, b->prec, b->bpw, b->bpc, flags + 1, st),
+                               b->dtype, b->prec, b->shape, b->bpc, flags + 1, st),
          "batch contraction");
   if (pe) CG_HIP(hipEventRecord(pe->second, st), "event record");
   return CG_OK;
@@ -452,14 +452,14 @@ cg_status cg_batch_tune(cg_batch* b, const cg_batch_job* in, int32_t reps, void*
   const bool prof = b->prof;
   b->prof = false;
   float best = 1e30f;
-  int bb = b->bpw, bs = b->split, bc = b->bpc;
-  for (int bpw : {1, 2}) {
-    const int occ = cg::batch_max_blocks_per_cu(b->dtype, b->prec, bpw);
+  int bb = b->shape, bs = b->split, bc = b->bpc;
+  for (int shape = 0; shape < cg::kBatchShapes; ++shape) {
+    const int occ = cg::batch_max_blocks_per_cu(b->dtype, b->prec, shape);
     std::vector<int> shapes = {occ};
     if (occ > 1) shapes.push_back(1);
     for (int split : {0, 1}) {
       for (int bpc : shapes) {
-        b->bpw = bpw;
+        b->shape = shape;
         b->split = split;
         b->bpc = bpc;
         if ((s = build_items(b, in, st)) != CG_OK) break;
@@ -479,7 +479,7 @@ cg_status cg_batch_tune(cg_batch* b, const cg_batch_job* in, int32_t reps, void*
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
           best = ms;
-          bb = bpw;
+          bb = shape;
           bs = split;
           bc = bpc;
         }
@@ -491,7 +491,7 @@ cg_status cg_batch_tune(cg_batch* b, const cg_batch_job* in, int32_t reps, void*
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->prof = prof;
-  b->bpw = bb;
+  b->shape = bb;
   b->split = bs;
   b->bpc = bc;
   if (s != CG_OK) return s;
@@ -576,9 +576,10 @@ cg_status cg_batch_query(const cg_batch* b, int32_t what, int64_t* value) {
     case 2: *value = b->ntiles; break;
     case 3: *value = b->nitems; break;
     case 4: *value = b->last_ncand; break;
-    case 5: *value = 256 * (int64_t)b->bpw; break;
+    case 5: *value = cg::batch_shape_rows(b->shape); break;
     case 6: *value = b->split; break;
-    case 7: *value = b->bpc > 0 ? b->bpc : cg::batch_max_blocks_per_cu(b->dtype, b->prec, b->bpw); break;
+    case 7: *value = b->bpc > 0 ? b->bpc : cg::batch_max_blocks_per_cu(b->dtype, b->prec, b->shape); break;
+    case 9: *value = b->shape; break;
     case 8: *value = b->exec ? 1 : 0; break;
     default: return fail(CG_E_INVALID, "unknown query %d", what);
   }

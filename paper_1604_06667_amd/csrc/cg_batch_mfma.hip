@@ -17,10 +17,14 @@ __device__ __noinline__ double chord2_to_d2_exact(double c2) {
   return d * d;
 }
 
-constexpr int kBatchWaves = 8;
-
-template <int BPW, int MODE, typename T>
-__global__ void __launch_bounds__(kBatchWaves * 64) k_batch_mfma(
+// Launch shapes of the persistent kernel (chosen by the autotuner):
+// wavefronts per workgroup and 32-channel blocks per wavefront.
+//   shape 0: 8 x 1 (256 channels per item)    shape 1: 8 x 2 (512)
+//   shape 2: 4 x 1 (128)                      shape 3: 4 x 2 (256, two workgroups per CU)
+// (4-wavefront workgroups are held to two wavefronts per SIMD, so that two
+// of them share a compute unit and cover each other's barrier waits)
+template <int NW, int BPW, int MODE, typename T>
+__global__ void __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) k_batch_mfma(
     const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, int64_t nitems,
     int* counter, const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ cand,
     const uint32_t* __restrict__ crow, const double* __restrict__ cxyz, int64_t ncap,
@@ -57,12 +61,21 @@ __global__ void __launch_bounds__(kBatchWaves * 64) k_batch_mfma(
     ov.cst = jb.cst;
     ov.tst = jb.tst;
     ov.mode = ACC_FINAL;
-    mfma_tile<kBatchWaves, BPW, 2, MODE, false, T>(tv, jb.kp, (const T*)jb.data, zrow, jb.ld,
-                                                   jb.nchan, ov, item.tile, item.c0, item.cend);
+    mfma_tile<NW, BPW, 2, MODE, false, T>(tv, jb.kp, (const T*)jb.data, zrow, jb.ld, jb.nchan, ov,
+                                          item.tile, item.c0, item.cend);
   }
 }
 
-template <int BPW, int MODE, typename T>
+template <int NW, int BPW, int MODE, typename T>
+static int occ_of() {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_mfma<NW, BPW, MODE, T>, NW * 64,
+                                                   0) != hipSuccess)
+    return 0;
+  return occ;
+}
+
+template <int NW, int BPW, int MODE, typename T>
 static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
                             int* counter, const uint64_t* cand_off, const uint32_t* cand,
                             const uint32_t* crow, const double* cxyz, int64_t ncap,
@@ -71,103 +84,96 @@ static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, int64_
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  int occ = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_mfma<BPW, MODE, T>,
-                                                   kBatchWaves * 64, 0);
-  if (e != hipSuccess) return e;
+  const int occ = occ_of<NW, BPW, MODE, T>();
   int per = blocks_per_cu > 0 && blocks_per_cu < occ ? blocks_per_cu : occ;
   if (per < 1) per = 1;
   int64_t grid = (int64_t)ncu * per;
   if (grid > nitems) grid = nitems;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((k_batch_mfma<BPW, MODE, T>), dim3((unsigned)grid), dim3(kBatchWaves * 64), 0,
-                     st, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
+  hipLaunchKernelGGL((k_batch_mfma<NW, BPW, MODE, T>), dim3((unsigned)grid), dim3(NW * 64), 0, st,
+                     jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
                      (const T*)zrow, ovf);
   return hipGetLastError();
 }
 
 template <int MODE, typename T>
-static hipError_t launch_bp(int bpw, const BatchJob* jobs, const BatchItem* items, int64_t nitems,
-                            int* counter, const uint64_t* cand_off, const uint32_t* cand,
-                            const uint32_t* crow, const double* cxyz, int64_t ncap,
-                            const void* zrow, int blocks_per_cu, const int* ovf, hipStream_t st) {
-  switch (bpw) {
-    case 1:
-      return launch_bt<1, MODE, T>(jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
-                                   zrow, blocks_per_cu, ovf, st);
-    case 2:
-      return launch_bt<2, MODE, T>(jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
-                                   zrow, blocks_per_cu, ovf, st);
-    default:
-      return hipErrorInvalidValue;
-  }
-}
-
-template <int MODE>
-static hipError_t launch_bm(int dtype, int bpw, const BatchJob* jobs, const BatchItem* items,
+static hipError_t launch_bs(int shape, const BatchJob* jobs, const BatchItem* items,
                             int64_t nitems, int* counter, const uint64_t* cand_off,
                             const uint32_t* cand, const uint32_t* crow, const double* cxyz,
                             int64_t ncap, const void* zrow, int blocks_per_cu, const int* ovf,
                             hipStream_t st) {
-  switch (dtype) {
-    case 0:
-      return launch_bp<MODE, double>(bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
-                                     ncap, zrow, blocks_per_cu, ovf, st);
-    case 1:
-      return launch_bp<MODE, float>(bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
-                                    ncap, zrow, blocks_per_cu, ovf, st);
-    case 2:
-      return launch_bp<MODE, _Float16>(bpw, jobs, items, nitems, counter, cand_off, cand, crow,
-                                       cxyz, ncap, zrow, blocks_per_cu, ovf, st);
-    default:
-      return launch_bp<MODE, uint16_t>(bpw, jobs, items, nitems, counter, cand_off, cand, crow,
-                                       cxyz, ncap, zrow, blocks_per_cu, ovf, st);
+#define CG_BT(NW_, BPW_)                                                                     \
+  launch_bt<NW_, BPW_, MODE, T>(jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap, \
+                                zrow, blocks_per_cu, ovf, st)
+  switch (shape) {
+    case 0: return CG_BT(8, 1);
+    case 1: return CG_BT(8, 2);
+    case 2: return CG_BT(4, 1);
+    case 3: return CG_BT(4, 2);
+    default: return hipErrorInvalidValue;
   }
+#undef CG_BT
+}
+
+template <int MODE>
+static hipError_t launch_bm(int dtype, int shape, const BatchJob* jobs, const BatchItem* items,
+                            int64_t nitems, int* counter, const uint64_t* cand_off,
+                            const uint32_t* cand, const uint32_t* crow, const double* cxyz,
+                            int64_t ncap, const void* zrow, int blocks_per_cu, const int* ovf,
+                            hipStream_t st) {
+#define CG_BS(T_)                                                                                \
+  launch_bs<MODE, T_>(shape, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap, zrow, \
+                      blocks_per_cu, ovf, st)
+  switch (dtype) {
+    case 0: return CG_BS(double);
+    case 1: return CG_BS(float);
+    case 2: return CG_BS(_Float16);
+    default: return CG_BS(uint16_t);
+  }
+#undef CG_BS
 }
 
 hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
                              int* counter, const uint64_t* cand_off, const uint32_t* cand,
                              const uint32_t* crow, const double* cxyz, int64_t ncap,
-                             const void* zrow, int dtype, int prec, int bpw, int blocks_per_cu,
+                             const void* zrow, int dtype, int prec, int shape, int blocks_per_cu,
                              const int* ovf, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (prec == 2)
-    return launch_bm<1>(dtype, bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
-                        zrow, blocks_per_cu, ovf, st);
-  return launch_bm<0>(dtype, bpw, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
-                      zrow, blocks_per_cu, ovf, st);
-}
-
-template <int BPW, int MODE, typename T>
-static int occ_of() {
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_mfma<BPW, MODE, T>,
-                                                   kBatchWaves * 64, 0) != hipSuccess)
-    return 0;
-  return occ;
+    return launch_bm<1>(dtype, shape, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
+                        ncap, zrow, blocks_per_cu, ovf, st);
+  return launch_bm<0>(dtype, shape, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
+                      ncap, zrow, blocks_per_cu, ovf, st);
 }
 
 template <int MODE, typename T>
-static int occ_b(int bpw) {
-  switch (bpw) {
-    case 1: return occ_of<1, MODE, T>();
-    case 2: return occ_of<2, MODE, T>();
+static int occ_s(int shape) {
+  switch (shape) {
+    case 0: return occ_of<8, 1, MODE, T>();
+    case 1: return occ_of<8, 2, MODE, T>();
+    case 2: return occ_of<4, 1, MODE, T>();
+    case 3: return occ_of<4, 2, MODE, T>();
     default: return 0;
   }
 }
 
 template <int MODE>
-static int occ_m(int dtype, int bpw) {
+static int occ_m(int dtype, int shape) {
   switch (dtype) {
-    case 0: return occ_b<MODE, double>(bpw);
-    case 1: return occ_b<MODE, float>(bpw);
-    case 2: return occ_b<MODE, _Float16>(bpw);
-    default: return occ_b<MODE, uint16_t>(bpw);
+    case 0: return occ_s<MODE, double>(shape);
+    case 1: return occ_s<MODE, float>(shape);
+    case 2: return occ_s<MODE, _Float16>(shape);
+    default: return occ_s<MODE, uint16_t>(shape);
   }
 }
 
-int batch_max_blocks_per_cu(int dtype, int prec, int bpw) {
-  return prec == 2 ? occ_m<1>(dtype, bpw) : occ_m<0>(dtype, bpw);
+int batch_max_blocks_per_cu(int dtype, int prec, int shape) {
+  return prec == 2 ? occ_m<1>(dtype, shape) : occ_m<0>(dtype, shape);
+}
+
+int batch_shape_rows(int shape) {
+  static const int rows[4] = {256, 512, 128, 256};
+  return shape >= 0 && shape < 4 ? rows[shape] : 0;
 }
 
 }  // namespace cg

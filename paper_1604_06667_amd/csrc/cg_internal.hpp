@@ -261,14 +261,17 @@ hipError_t launch_batch_expand(const BatchJob* jobs, const int64_t* toff, int nj
                                const uint64_t* cand_off, const uint32_t* vals, const double* sx,
                                int64_t nsorted, uint32_t* cand, uint32_t* crow, double* cxyz,
                                int64_t ncap, const int* ovf, hipStream_t st);
-// Persistent contraction over a queue of items (bpw 1 or 2: at most 256 * bpw
-// channels per item); counter must be zero at launch.
+// Persistent contraction over a queue of items; shape 0..3 selects the
+// workgroup (8 or 4 wavefronts, 1 or 2 channel blocks each: at most
+// batch_shape_rows(shape) channels per item); counter must be zero at launch.
+constexpr int kBatchShapes = 4;
 hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
                              int* counter, const uint64_t* cand_off, const uint32_t* cand,
                              const uint32_t* crow, const double* cxyz, int64_t ncap,
-                             const void* zrow, int dtype, int prec, int bpw, int blocks_per_cu,
+                             const void* zrow, int dtype, int prec, int shape, int blocks_per_cu,
                              const int* ovf, hipStream_t st);
-int batch_max_blocks_per_cu(int dtype, int prec, int bpw);
+int batch_max_blocks_per_cu(int dtype, int prec, int shape);
+int batch_shape_rows(int shape);
 hipError_t launch_stats(const TileView& tv, const KernelParams& kp, const int32_t* slot_target,
                         int32_t* counts, uint64_t* hashes, hipStream_t st);
 hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
