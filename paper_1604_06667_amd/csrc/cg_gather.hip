@@ -44,8 +44,13 @@ __device__ __forceinline__ void target_axes(const KernelParams& kp, double lon, 
 __device__ __forceinline__ float qnan_f() { return __int_as_float(0x7fc00000); }
 
 // ---------------------------------------------------------------------------
-// Narrow data (nchan <= CMAX <= 16): one lane per target, candidates and
-// their (sorted, FP32) data rows staged in LDS and broadcast to all lanes.
+// Narrow data (nchan <= CMAX <= 16): one lane per target.  A chunk of
+// candidates and their (sorted, FP32) data rows is staged in LDS; each lane
+// first marks, in a 64-bit mask, the candidates within the support of its
+// target (FP64 test), then walks only its own marked candidates: weight and
+// channel products for those pairs alone, with no lane idling on the pairs
+// of other targets.  Sums per lane run in candidate order, as in the
+// definition.
 
 template <int CMAX>
 __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
@@ -78,20 +83,27 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
         if (c < nchan) s_d[lane * CMAX + c] = sdata[pos * nchan + c];
     }
     __syncthreads();
+    // candidates of the chunk within the support of this lane's target
+    uint64_t inside = 0;
+    for (int k = 0; k < kmax; ++k) {
+      const double dx = s_x[k] - tx, dy = s_y[k] - ty, dz = s_z[k] - tz;
+      const double c2 = dx * dx + dy * dy + dz * dz;
+      if (c2 <= kp.cs2) inside |= 1ull << k;
+    }
     float p[CMAX];
 #pragma unroll
     for (int c = 0; c < CMAX; ++c) p[c] = 0.0f;
     float pw = 0.0f;
-    for (int k = 0; k < kmax; ++k) {
+    while (inside) {
+      const int k = __builtin_ctzll(inside);
+      inside &= inside - 1;
       const double dx = s_x[k] - tx, dy = s_y[k] - ty, dz = s_z[k] - tz;
       const double c2 = dx * dx + dy * dy + dz * dz;
-      if (c2 <= kp.cs2) {
-        const float w = pair_weight(kp, c2, dx, dy, dz, ax[0], ax[1], ax[2], bx[0], bx[1], bx[2]);
-        pw += w;
+      const float w = pair_weight(kp, c2, dx, dy, dz, ax[0], ax[1], ax[2], bx[0], bx[1], bx[2]);
+      pw += w;
 #pragma unroll
-        for (int c = 0; c < CMAX; ++c)
-          if (c < nchan) p[c] = fmaf(w, s_d[k * CMAX + c], p[c]);
-      }
+      for (int c = 0; c < CMAX; ++c)
+        if (c < nchan) p[c] = fmaf(w, s_d[k * CMAX + c], p[c]);
     }
     wacc += (double)pw;
 #pragma unroll
