@@ -294,7 +294,7 @@ def run_allsky(a, dev):
     cpu, extra = None, {}
     if not a.no_cpu:
         # a block of targets across the 0/360 seam on the equator
-        k = 256
+        k = 768
         y0, x0 = ny // 2 - k // 2, nx // 2 - k // 2
         xs, ys = np.meshgrid(np.arange(x0, x0 + k), np.arange(y0, y0 + k))
         cpu, errs = cpu_baseline(wl, (ys * nx + xs).ravel(),
@@ -356,10 +356,10 @@ def run_sightlines(a, dev):
         extra["speedup_vs_fp32"] = round(res["fp32"][0] / ms, 3)
     cpu = None
     if not a.no_cpu:
-        # targets in a 1.2 x 1.2 deg box at the field centre
+        # targets in a 3.6 x 3.6 deg box at the field centre
         tl, tb = np.asarray(wl.target["lon"]), np.asarray(wl.target["lat"])
-        sel = np.nonzero((np.abs(tl - 120.0) < 0.6) & (np.abs(tb - 30.0) < 0.6))[0]
-        cpu, errs = cpu_baseline(wl, sel, "sight lines in a 1.2x1.2 deg box at (120, 30)", cubes)
+        sel = np.nonzero((np.abs(tl - 120.0) < 1.8) & (np.abs(tb - 30.0) < 1.8))[0]
+        cpu, errs = cpu_baseline(wl, sel, "sight lines in a 3.6x3.6 deg box at (120, 30)", cubes)
         extra["e_val"] = errs
     out = base_line(a, ("sight lines: 10,000,000 samples x 256 BF16 channels over 30x30 deg -> "
                         "2,000,000 targets, gauss2d 3'x2' PA 30, support 9', nside 4096"),
@@ -429,12 +429,12 @@ def run_batched(a, dev):
                        "workgroups_per_cu": b.query(7), "shape": b.query(9), "items": b.query(3)}}
     cpu = None
     if not a.no_cpu:
-        # the largest job's central 48x48 targets
+        # the largest job's central 64x64 targets
         j = int(np.argmax([wl.nsamples for wl in wls]))
         wl = wls[j]
         nx = wl.target["wcs"]["naxis1"]
         ny = wl.target["wcs"]["naxis2"]
-        k = min(48, nx, ny)
+        k = min(64, nx, ny)
         x0, y0 = (nx - k) // 2, (ny - k) // 2
         xs, ys = np.meshgrid(np.arange(x0, x0 + k), np.arange(y0, y0 + k))
         cpu, errs = cpu_baseline(wl, (ys * nx + xs).ravel(),
