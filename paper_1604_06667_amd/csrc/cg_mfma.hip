@@ -26,7 +26,7 @@ __device__ __noinline__ double chord2_to_d2_exact(double c2) {
 
 bool mfma_available() { return true; }
 
-template <int NW, int BPW, int KT, int MODE, bool FULL, typename T>
+template <int NW, int BPW, int KT, int MODE, bool FULL, typename T, int KS>
 __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelParams kp,
                                                          const T* __restrict__ data,
                                                          const T* __restrict__ zrow, int64_t ld,
@@ -37,10 +37,10 @@ __global__ void __launch_bounds__(NW * 64) k_gather_mfma(TileView tv, KernelPara
   if (tv.ntx > 0) tile = strip_tile(tile, tv.ntiles, tv.ntx);
   const int64_t c0 = pass * CP;
   const int64_t cend = c0 + CP < nchan ? c0 + CP : nchan;
-  mfma_tile<NW, BPW, KT, MODE, FULL, T>(tv, kp, data, zrow, ld, nchan, ov, tile, c0, cend);
+  mfma_tile<NW, BPW, KT, MODE, FULL, T, KS>(tv, kp, data, zrow, ld, nchan, ov, tile, c0, cend);
 }
 
-template <int NW, int BPW, int MODE, typename T>
+template <int NW, int BPW, int MODE, typename T, int KS>
 static void launch_cfg(const TileView& tv, const KernelParams& kp, const void* data,
                        const void* zrow, int64_t ld, int64_t nchan, const OutView& ov,
                        hipStream_t st) {
@@ -51,7 +51,7 @@ static void launch_cfg(const TileView& tv, const KernelParams& kp, const void* d
   const T* d = (const T*)data;
   const T* z = (const T*)zrow;
 #define CG_MFMA_LAUNCH(KT_, FULL_)                                                              \
-  hipLaunchKernelGGL((k_gather_mfma<NW, BPW, KT_, MODE, FULL_, T>), g, b, 0, st, tv, kp, d, z, \
+  hipLaunchKernelGGL((k_gather_mfma<NW, BPW, KT_, MODE, FULL_, T, KS>), g, b, 0, st, tv, kp, d, z, \
                      ld, nchan, ov)
   if (kp.type == 0) {
     if (full) CG_MFMA_LAUNCH(0, true);
@@ -67,11 +67,14 @@ template <int MODE, typename T>
 static void launch_dt(const TileView& tv, const KernelParams& kp, const void* data,
                       const void* zrow, int64_t ld, int64_t nchan, const OutView& ov,
                       hipStream_t st) {
-  if (nchan <= 64) launch_cfg<2, 1, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
-  else if (nchan <= 128) launch_cfg<4, 1, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
-  else if (nchan <= 256) launch_cfg<8, 1, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
-  else if (nchan <= 512) launch_cfg<8, 2, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
-  else launch_cfg<8, 4, MODE, T>(tv, kp, data, zrow, ld, nchan, ov, st);
+  // KS: 16-sample MFMA steps per pipeline stage.  Two per stage pay off at
+  // 512 channels per workgroup (more loads in flight per barrier); wider
+  // stages cost occupancy elsewhere.
+  if (nchan <= 64) launch_cfg<2, 1, MODE, T, 1>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else if (nchan <= 128) launch_cfg<4, 1, MODE, T, 1>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else if (nchan <= 256) launch_cfg<8, 1, MODE, T, 1>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else if (nchan <= 512) launch_cfg<8, 2, MODE, T, 2>(tv, kp, data, zrow, ld, nchan, ov, st);
+  else launch_cfg<8, 4, MODE, T, 1>(tv, kp, data, zrow, ld, nchan, ov, st);
 }
 
 template <int MODE>

@@ -99,14 +99,17 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, int nvalid, bool 
 // chunk, i.e. exactly its MFMA A operand, so the data never passes through
 // LDS: each lane loads its 8 values straight from the sample rows (one
 // 128-byte segment per row and half-wave) and converts them in registers.
-// Only the 64 x 16 weight block is shared through LDS (double buffered).
+// Only the 64 x MK weight block is shared through LDS (double buffered).
+// A chunk is KS consecutive 16-sample MFMA steps (MK = 16 KS candidates): a
+// larger chunk puts more loads in flight per barrier, which is what bounds
+// narrow channel ranges, at KS x 8 data registers per block.
 // Software pipeline, one barrier per chunk: while chunk i is on the matrix
 // cores, the same wavefront computes the weight block of chunk i+1 and
 // reloads its data registers with chunk i+1; candidate records run two
 // chunks ahead through a three-deep LDS ring.  Past-the-end candidates point
 // at a row of zeros, so the loads need no bounds selects.  FULL: the channel
 // count is a multiple of CP (no channel bounds checks).
-template <int NW, int BPW, int KT, int MODE, bool FULL, typename T>
+template <int NW, int BPW, int KT, int MODE, bool FULL, typename T, int KS = 1>
 __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams kp,
                                           const T* __restrict__ data, const T* __restrict__ zrow,
                                           int64_t ld, int64_t nchan, const OutView ov,
@@ -116,7 +119,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   constexpr bool SPLIT = MODE == 0;
   constexpr bool BF16IN = std::is_same<T, uint16_t>::value;
   constexpr int NS = SPLIT ? 2 : 1;              // hi (+ lo) parts
-  constexpr int MK = 16;                         // candidate samples per chunk
+  constexpr int MK = 16 * KS;                    // candidate samples per chunk
+  static_assert(MK <= NW * 64, "one candidate record per thread");
   constexpr int KP = MK + 8;                     // padded LDS row of the weight block
   constexpr int CP = NW * BPW * 32;              // channels per pass
   using opv_t = typename std::conditional<F16, f16x8_t, bf16x8_t>::type;
@@ -126,7 +130,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   __shared__ double s_red[2][NW][kTile];
   __shared__ double s_wfin[2][kTile];
   __shared__ double s_tg[kTile][3];                    // target unit vectors
-  __shared__ float s_ax[KT == 0 ? 1 : kTile][6];       // major, minor axis (elliptical)
+  __shared__ float s_ax[KT == 0 ? 1 : kTile][3];       // major axis at the target (elliptical)
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t ns = tv.nslots;
@@ -152,7 +156,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     s_tg[t][1] = tv.txyz[ns + wslot];
     s_tg[t][2] = tv.txyz[2 * ns + wslot];
     if constexpr (KT != 0) {
-      double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+      // major axis: north turned towards east by the position angle
+      double a[3] = {0.0, 0.0, 0.0};
       if (ell && isfinite(x)) {
         double sa, ca, sd, cd;
         sincos(tv.tll[wslot], &sa, &ca);
@@ -161,15 +166,9 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
         a[0] = kp.cospa * nx + kp.sinpa * ex;
         a[1] = kp.cospa * ny + kp.sinpa * ey;
         a[2] = kp.cospa * nz;
-        b[0] = kp.cospa * ex - kp.sinpa * nx;
-        b[1] = kp.cospa * ey - kp.sinpa * ny;
-        b[2] = -kp.sinpa * nz;
       }
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        s_ax[t][q] = (float)a[q];
-        s_ax[t][3 + q] = (float)b[q];
-      }
+      for (int q = 0; q < 3; ++q) s_ax[t][q] = (float)a[q];
     }
   }
   // this thread's target in the weight block and its candidates kg, kg + NW, ...
@@ -219,25 +218,40 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   // Kernel value of a pair.  The support test is FP64 on the chord; the
   // value itself only needs FP32 accuracy (it is rounded to 16-bit operand
   // parts), so the distance series, the elliptical form and the exponential
-  // are evaluated in FP32, branch-free, and masked by the test.
-  const float k1f = (float)kp.k1, kmajf = (float)kp.kmaj, kminf = (float)kp.kmin;
+  // are evaluated in FP32 and masked by the test.
+  //
+  // Elliptical kernel: with u, v the components of the chord along the
+  // major and minor axes at the target (both tangent there), u^2 + v^2 is
+  // the chord's tangential part c^2 (1 - c^2/4) exactly, so the exponent
+  //   d^2 (u^2 kmaj + v^2 kmin) / (u^2 + v^2)
+  // equals d^2 kmin + (kmaj - kmin) u^2 rq with rq = d^2 / (c^2 (1 - c^2/4)),
+  // which needs only u.  Supports below ~0.57 deg (c^2 <= 1e-4, uniform over
+  // the launch) take the two leading terms of d^2 = c^2 (1 + c^2/12 + ...)
+  // and rq = 1 + c^2/3 + ..., whose next terms are below 1e-8 relative.
+  const float k1f = (float)kp.k1, kminf = (float)kp.kmin, kdf = (float)(kp.kmaj - kp.kmin);
+  const bool short_support = kp.cs2 <= 1e-4;
   auto weight = [&](int rb, int wb, int k) {
     const double dx = s_c[rb][k][0] - s_tg[nw][0];
     const double dy = s_c[rb][k][1] - s_tg[nw][1];
     const double dz = s_c[rb][k][2] - s_tg[nw][2];
     const double c2 = dx * dx + dy * dy + dz * dz;
     const float c = (float)c2;
-    float d2 = c * (1.0f + c * (1.0f / 12.0f + c * (1.0f / 90.0f + c * (1.0f / 560.0f +
-                    c * (1.0f / 3150.0f + c * (1.0f / 16632.0f))))));
-    if (c2 > 0.1225) d2 = (float)chord2_to_d2_exact(c2);   // chords beyond ~20 deg
+    float d2, rq;
+    if (short_support) {
+      d2 = c + c * c * (1.0f / 12.0f);
+      rq = 1.0f + c * (1.0f / 3.0f);
+    } else {
+      d2 = c * (1.0f + c * (1.0f / 12.0f + c * (1.0f / 90.0f + c * (1.0f / 560.0f +
+               c * (1.0f / 3150.0f + c * (1.0f / 16632.0f))))));
+      if (c2 > 0.1225) d2 = (float)chord2_to_d2_exact(c2);   // chords beyond ~20 deg
+      const float uv = c * (1.0f - 0.25f * c);
+      rq = uv > 0.0f ? d2 * __builtin_amdgcn_rcpf(uv) : 1.0f;
+    }
     float x = d2 * k1f;
     if constexpr (KT != 0) {
       if (ell) {
-        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-        const float u = fx * s_ax[nw][0] + fy * s_ax[nw][1] + fz * s_ax[nw][2];
-        const float v = fx * s_ax[nw][3] + fy * s_ax[nw][4] + fz * s_ax[nw][5];
-        const float uu = u * u, vv = v * v, uv = uu + vv;
-        x = uv > 0.0f ? d2 * (uu * kmajf + vv * kminf) * __builtin_amdgcn_rcpf(uv) : 0.0f;
+        const float u = (float)dx * s_ax[nw][0] + (float)dy * s_ax[nw][1] + (float)dz * s_ax[nw][2];
+        x = d2 * kminf + kdf * (u * u) * rq;
       }
     }
     const float w = c2 <= kp.cs2 ? __builtin_amdgcn_exp2f(-x) : 0.0f;
@@ -253,12 +267,27 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     wsum_r += (double)wr;
   };
   // this lane's A-operand values (raw input) of one chunk
-  float raw[BPW][8];
+  // 16-bit input of the operand's own type is used bit for bit (two values
+  // packed per register); any other input is converted through FP32.
+  constexpr bool DIRECT = (BF16IN && !F16) || (std::is_same<T, _Float16>::value && F16);
+  float raw[BPW][KS][DIRECT ? 1 : 8];
+  uint32_t rawp[BPW][KS][4];
   auto load_block = [&](int rb, int b) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const T* p = data + (s_row[rb][8 * kh + i] + cbase + 32 * b);
-      raw[b][i] = bvalid[b] ? in_f32<T>(p) : 0.0f;
+    for (int s = 0; s < KS; ++s) {
+      const int64_t* rw = &s_row[rb][16 * s + 8 * kh];
+      const int64_t cofs = cbase + 32 * b;
+      if constexpr (DIRECT) {
+        const uint16_t* d16 = reinterpret_cast<const uint16_t*>(data);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t lo = d16[rw[2 * q] + cofs], hi = d16[rw[2 * q + 1] + cofs];
+          rawp[b][s][q] = bvalid[b] ? __builtin_amdgcn_perm(hi, lo, 0x05040100u) : 0u;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) raw[b][s][i] = bvalid[b] ? in_f32<T>(data + (rw[i] + cofs)) : 0.0f;
+      }
     }
   };
 
@@ -279,60 +308,80 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     for (int b = 0; b < BPW; ++b) load_block(0, b);
   }
 
+  int r1 = 1, r2 = 2;   // record buffers of chunks ch+1, ch+2 (ring of three)
   for (int64_t ch = 0; ch < nchunks; ++ch) {
     const int wc = (int)(ch & 1);                 // weight buffer of chunk ch
-    const int r1 = (int)((ch + 1) % 3);           // record buffer of chunk ch+1
     __syncthreads();
     // records: publish chunk ch+2, fetch chunk ch+3
     if (t < MK) {
-      put_rec((int)((ch + 2) % 3));
+      put_rec(r2);
       load_rec(ch + 3);
     }
     const int kofs = 8 * kh;
-    opv_t bop[NS][2];
+    // weight operands of MFMA step s (step 0 read once and shared by the blocks)
+    auto load_bop = [&](int s, opv_t (&bo)[NS][2]) {
 #pragma unroll
-    for (int sp = 0; sp < NS; ++sp)
+      for (int sp = 0; sp < NS; ++sp)
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-        bop[sp][nb] = *reinterpret_cast<const opv_t*>(&s_wt[wc][sp][(nb * 32 + cl) * KP + kofs]);
+        for (int nb = 0; nb < 2; ++nb)
+          bo[sp][nb] = *reinterpret_cast<const opv_t*>(&s_wt[wc][sp][(nb * 32 + cl) * KP + 16 * s + kofs]);
+    };
+    opv_t bop0[NS][2];
+    load_bop(0, bop0);
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
       // this lane's data of chunk ch -> MFMA operands (hi, lo); refill with chunk ch+1
-      opv_t aop[NS];
-      {
+      opv_t aop[KS][NS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
         uint32_t hp[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) hp[q] = cvt_pk<F16>(raw[b][2 * q], raw[b][2 * q + 1]);
-        aop[0] = __builtin_bit_cast(opv_t, hp);
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (DIRECT) hp[q] = rawp[b][s][q];
+          else hp[q] = cvt_pk<F16>(raw[b][s][2 * q], raw[b][s][2 * q + 1]);
+        }
+        aop[s][0] = __builtin_bit_cast(opv_t, hp);
         if constexpr (SPLIT && !BF16IN) {
           uint32_t lp[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            lp[q] = cvt_pk<F16>(raw[b][2 * q] - unpk_lo<F16>(hp[q]),
-                                raw[b][2 * q + 1] - unpk_hi<F16>(hp[q]));
-          aop[NS - 1] = __builtin_bit_cast(opv_t, lp);
+            lp[q] = cvt_pk<F16>(raw[b][s][2 * q] - unpk_lo<F16>(hp[q]),
+                                raw[b][s][2 * q + 1] - unpk_hi<F16>(hp[q]));
+          aop[s][NS - 1] = __builtin_bit_cast(opv_t, lp);
         }
       }
       load_block(r1, b);   // past the last chunk this reads the zero row
       // independent accumulators back to back; the residual products last
-      if (!bany[b]) {
-        // no channel of this block: nothing to accumulate
-      } else if constexpr (F16) {
+      if (bany[b]) {
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
-      } else {
+        for (int s = 0; s < KS; ++s) {
+          opv_t bop[NS][2];
+          if (s == 0) {
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[0][nb], acc[b][nb], 0, 0, 0);
-        if constexpr (SPLIT) {
+            for (int sp = 0; sp < NS; ++sp)
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-            acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[0], bop[1][nb], acc[b][nb], 0, 0, 0);
-          if constexpr (!BF16IN) {
+              for (int nb = 0; nb < 2; ++nb) bop[sp][nb] = bop0[sp][nb];
+          } else {
+            load_bop(s, bop);
+          }
+          if constexpr (F16) {
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb)
-              acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[1], bop[0][nb], acc[b][nb], 0, 0, 0);
+              acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aop[s][0], bop[0][nb], acc[b][nb], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+              acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[s][0], bop[0][nb], acc[b][nb], 0, 0, 0);
+            if constexpr (SPLIT) {
+#pragma unroll
+              for (int nb = 0; nb < 2; ++nb)
+                acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[s][0], bop[1][nb], acc[b][nb], 0, 0, 0);
+              if constexpr (!BF16IN) {
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                  acc[b][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[s][1], bop[0][nb], acc[b][nb], 0, 0, 0);
+              }
+            }
           }
         }
       }
@@ -341,6 +390,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 #pragma unroll
       for (int k = kg + b * NW; k < MK; k += BPW * NW) weight(r1, wc ^ 1, k);
     }
+    r1 = r2;
+    r2 = r2 == 2 ? 0 : r2 + 1;
   }
   __syncthreads();
 
