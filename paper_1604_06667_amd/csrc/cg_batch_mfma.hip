@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) k_batch_mfma(
     ov.cst = jb.cst;
     ov.tst = jb.tst;
     ov.mode = ACC_FINAL;
-    mfma_tile<NW, BPW, 2, MODE, false, T>(tv, jb.kp, (const T*)jb.data, zrow, jb.ld, jb.nchan, ov,
+    mfma_tile<NW, BPW, 2, MODE, false, T, 1, true>(tv, jb.kp, (const T*)jb.data, zrow, jb.ld, jb.nchan, ov,
                                           item.tile, item.c0, item.cend);
   }
 }

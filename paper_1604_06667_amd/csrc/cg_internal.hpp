@@ -44,6 +44,21 @@ struct TileView {
 // is given the k-th contiguous run of tiles, walked in order, so that tiles
 // sharing candidate samples are resident together in that XCD's L2.
 constexpr int kNumXcd = 8;
+
+// Accesses through a pointer that addresses device global memory.  With GL
+// set the pointer is cast to the global address space first: pointers read
+// from memory (a job table) have no known address space, and the compiler
+// would otherwise issue flat accesses, which also wait on the LDS counter.
+template <bool GL, typename T>
+__device__ __forceinline__ T ldg(const T* p, int64_t i) {
+  if constexpr (GL) return ((const T __attribute__((address_space(1)))*)p)[i];
+  else return p[i];
+}
+template <bool GL, typename T>
+__device__ __forceinline__ void stg(T* p, int64_t i, T v) {
+  if constexpr (GL) ((T __attribute__((address_space(1)))*)p)[i] = v;
+  else p[i] = v;
+}
 __device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t ntiles) {
   const int64_t k = b % kNumXcd;
   const int64_t j = b / kNumXcd;

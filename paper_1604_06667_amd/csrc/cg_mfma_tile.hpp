@@ -109,7 +109,7 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, int nvalid, bool 
 // chunks ahead through a three-deep LDS ring.  Past-the-end candidates point
 // at a row of zeros, so the loads need no bounds selects.  FULL: the channel
 // count is a multiple of CP (no channel bounds checks).
-template <int NW, int BPW, int KT, int MODE, bool FULL, typename T, int KS = 1>
+template <int NW, int BPW, int KT, int MODE, bool FULL, typename T, int KS = 1, bool GL = false>
 __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams kp,
                                           const T* __restrict__ data, const T* __restrict__ zrow,
                                           int64_t ld, int64_t nchan, const OutView ov,
@@ -151,17 +151,17 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 
   if (t < kTile) {
     const int64_t wslot = tile * kTile + t;
-    const double x = tv.txyz[wslot];
+    const double x = ldg<GL>(tv.txyz, wslot);
     s_tg[t][0] = x;
-    s_tg[t][1] = tv.txyz[ns + wslot];
-    s_tg[t][2] = tv.txyz[2 * ns + wslot];
+    s_tg[t][1] = ldg<GL>(tv.txyz, ns + wslot);
+    s_tg[t][2] = ldg<GL>(tv.txyz, 2 * ns + wslot);
     if constexpr (KT != 0) {
       // major axis: north turned towards east by the position angle
       double a[3] = {0.0, 0.0, 0.0};
       if (ell && isfinite(x)) {
         double sa, ca, sd, cd;
-        sincos(tv.tll[wslot], &sa, &ca);
-        sincos(tv.tll[ns + wslot], &sd, &cd);
+        sincos(ldg<GL>(tv.tll, wslot), &sa, &ca);
+        sincos(ldg<GL>(tv.tll, ns + wslot), &sd, &cd);
         const double ex = -sa, ey = ca, nx = -sd * ca, ny = -sd * sa, nz = cd;
         a[0] = kp.cospa * nx + kp.sinpa * ex;
         a[1] = kp.cospa * ny + kp.sinpa * ey;
@@ -184,7 +184,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[b][nb][j] = 0.0f;
 
-  const uint64_t cb0 = tv.cand_off[tile], cb1 = tv.cand_off[tile + 1];
+  const uint64_t cb0 = ldg<GL>(tv.cand_off, tile), cb1 = ldg<GL>(tv.cand_off, tile + 1);
   const int64_t nchunks = (int64_t)((cb1 - cb0 + MK - 1) / MK);
 
   // candidate record of chunk ch for thread t < MK (NaN / zero row past the end)
@@ -199,10 +199,10 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     const uint64_t idx = (uint64_t)ch * MK + t;
     const uint64_t q = rev ? cb1 - 1 - idx : cb0 + idx;
     if (ch < nchunks && idx < cb1 - cb0) {
-      rx = tv.cxyz[q];
-      ry = tv.cxyz[cap + q];
-      rz = tv.cxyz[2 * cap + q];
-      rrow = (int64_t)tv.crow[q] * ld;
+      rx = ldg<GL>(tv.cxyz, q);
+      ry = ldg<GL>(tv.cxyz, cap + q);
+      rz = ldg<GL>(tv.cxyz, 2 * cap + q);
+      rrow = (int64_t)ldg<GL>(tv.crow, q) * ld;
     } else {
       rx = ry = rz = nan;
       rrow = zoff;   // + channel offsets below stays inside the zero row
@@ -281,12 +281,19 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
         const uint16_t* d16 = reinterpret_cast<const uint16_t*>(data);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const uint32_t lo = d16[rw[2 * q] + cofs], hi = d16[rw[2 * q + 1] + cofs];
+          const uint32_t lo = ldg<GL>(d16, rw[2 * q] + cofs), hi = ldg<GL>(d16, rw[2 * q + 1] + cofs);
           rawp[b][s][q] = bvalid[b] ? __builtin_amdgcn_perm(hi, lo, 0x05040100u) : 0u;
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) raw[b][s][i] = bvalid[b] ? in_f32<T>(data + (rw[i] + cofs)) : 0.0f;
+        for (int i = 0; i < 8; ++i) {
+          if constexpr (GL) {
+            const T v = ldg<GL>(data, rw[i] + cofs);
+            raw[b][s][i] = bvalid[b] ? in_f32<T>(&v) : 0.0f;
+          } else {
+            raw[b][s][i] = bvalid[b] ? in_f32<T>(data + (rw[i] + cofs)) : 0.0f;
+          }
+        }
       }
     }
   };
@@ -418,7 +425,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       const int n = nb * 32 + (lane & 31);
-      const int32_t tg = ov.slot_target[tile * kTile + n];
+      const int32_t tg = ldg<GL>(ov.slot_target, tile * kTile + n);
       if (tg >= 0) {
         const double wr = s_wfin[1][n];
         const float inv = wr > 0.0 ? (float)(1.0 / wr) : 0.0f;
@@ -431,7 +438,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
             const int m = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
             const int64_t c = c0 + (wv * BPW + b) * 32 + m;
             if (!FULL && c >= cend) continue;
-            dst[c * ov.cst] = filled ? acc[b][nb][j] * inv : __int_as_float(0x7fc00000);
+            stg<GL>(dst, c * ov.cst, filled ? acc[b][nb][j] * inv : __int_as_float(0x7fc00000));
           }
         }
       }
@@ -458,8 +465,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   if (c0 == 0 && t < kTile) {
     const int64_t slot = tile * kTile + t;
     if (fin) {
-      const int32_t tg = ov.slot_target[slot];
-      if (tg >= 0 && ov.wout) ov.wout[tg] = (float)s_wfin[0][t];
+      const int32_t tg = ldg<GL>(ov.slot_target, slot);
+      if (tg >= 0 && ov.wout) stg<GL>(ov.wout, tg, (float)s_wfin[0][t]);
     } else if (ov.mode == ACC_ADD) {
       ov.W[slot] += s_wfin[0][t];
       ov.Wn[slot] += s_wfin[1][t];
