@@ -23,6 +23,7 @@ Modules
 -------
 ``sphere``   unit vectors, Vincenty distance, bearing (spherical trigonometry)
 ``wcs``      FITS-WCS pixel -> world for CAR (non-oblique) and SIN
+``healpix``  HEALPix pixel centres (RING and NESTED order) as map targets
 ``grid``     brute force (all pairs) and cKDTree-accelerated gridding,
              neighbour-set statistics
 ``metrics``  error measures used by the parity tests and the benchmark
@@ -34,6 +35,7 @@ pixels NaN, peak-one Gaussian, bearing measured at the target).
 
 from .sphere import unit_vectors, vincenty, bearing, splitmix64  # noqa: F401
 from .wcs import wcs_world, wcs_targets  # noqa: F401
+from .healpix import ring_centres, nest_centres  # noqa: F401
 from .grid import (grid_bruteforce, grid_kdtree, kernel_weight,  # noqa: F401
                    neighbour_sets, grid_workload, targets_of)
 from .metrics import e_val, e_weights, pointwise_rel  # noqa: F401

@@ -39,6 +39,7 @@ import numpy as np
 
 from .sphere import vincenty, bearing, splitmix64, unit_vectors
 from .wcs import wcs_targets
+from .healpix import centres as healpix_centres
 
 BAND_RAD = 1e-12   # samples this close to the support edge may go either way
 
@@ -252,10 +253,13 @@ def grid_kdtree(lon, lat, data, tlon, tlat, kernel, support, block=4096,
 
 
 def targets_of(wl):
-    """Target (lon, lat) arrays of a workload: WCS pixel centres or sight lines."""
+    """Target (lon, lat) arrays of a workload: WCS pixel centres, HEALPix
+    pixel centres or sight lines."""
     t = wl.target
     if t["kind"] == "wcs":
         return wcs_targets(t["wcs"])
+    if t["kind"] == "healpix":
+        return healpix_centres(t["nside"], t.get("order", "ring"))
     return np.asarray(t["lon"], dtype=np.float64), np.asarray(t["lat"], dtype=np.float64)
 
 
