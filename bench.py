@@ -24,6 +24,10 @@ Workloads (``--workload``; all synthetic, seeded):
 * ``sightlines``: 10,000,000 samples x 256 BF16 channels over 30x30 deg onto
   2,000,000 arbitrary target positions, elliptical Gaussian 3'x2' PA 30 deg,
   support 9', nside 4096; BF16, FP16 and FP32 contractions.
+* ``healpix``: the paper's App. A.1 simulation: ~47 M samples uniform on the
+  sphere (15 per map pixel), point sources through a 27.5' PSF plus noise
+  (2 FP32 channels), onto every pixel centre of the nside = 512 HEALPix map;
+  kernel FWHM 13.7', support 3 sigma; FP32 path.
 
 Prints one JSON line.  ``value`` = sample-channel contributions per second =
 (number of (target, sample) pairs with d <= support) x channels / time per
@@ -183,6 +187,8 @@ def make_gridder(wl, dev):
     import paper_1604_06667_amd as cgp
     if wl.target["kind"] == "wcs":
         g = cgp.WcsGrid(header_of(wl.target["wcs"], wl.nchan))
+    elif wl.target["kind"] == "healpix":
+        g = cgp.HpxGrid(wl.target["nside"], wl.target.get("order", "ring"), wl.nchan)
     else:
         tl = torch.as_tensor(np.asarray(wl.target["lon"], dtype=np.float64), device=dev)
         tb = torch.as_tensor(np.asarray(wl.target["lat"], dtype=np.float64), device=dev)
@@ -307,6 +313,44 @@ def run_allsky(a, dev):
                     {"samples": wl.nsamples, "targets": nx * ny, "channels": wl.nchan,
                      "nside": g.nside, "pairs": pairs, "contributions": contributions,
                      "contraction": "fp32"}, roof, cpu)
+    out.update(extra)
+    return out
+
+
+def run_healpix(a, dev):
+    import torch
+    import synth
+    t0 = time.time()
+    wl = synth.config_hpx(device=dev)
+    lon, lat, data = device_inputs(wl, dev)
+    torch.cuda.synchronize()
+    log(f"workload built in {time.time() - t0:.1f}s: {wl.name}")
+    g = make_gridder(wl, dev)
+    g.set_precision("fp32")
+    pairs, contributions = count_contributions(g, lon, lat, wl.nchan)
+    nt = wl.ntargets()
+    cube = torch.empty((wl.nchan, nt), dtype=torch.float32, device=dev)
+    weights = torch.empty((nt,), dtype=torch.float32, device=dev)
+    ms, kms, nl = time_path(g, lon, lat, data, cube, weights, a.steps, a.warmup)
+    log(f"fp32: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
+    roof = roof_alu(2.0 * contributions + FLOPS_PER_PAIR * pairs, kms, "contraction_healpix_fp32")
+    roof["alg_bytes"] = int(wl.nsamples * (wl.nchan * 4 + 16) + nt * (wl.nchan * 4 + 4))
+    cpu, extra = None, {}
+    if not a.no_cpu:
+        import oracle
+        tl, tb = oracle.targets_of(wl)
+        tidx = np.nonzero((tb > 0.0) & (tb < 40.0) & (tl > 170.0) & (tl < 230.0))[0]
+        cpu, errs = cpu_baseline(wl, tidx, "the map pixels with 0 < lat < 40 and 170 < lon < 230 deg",
+                                 {"fp32": cube})
+        extra["e_val"] = errs
+    nside = wl.target["nside"]
+    out = base_line(a, (f"HEALPix map (App. A.1): {wl.nsamples:,} uniform samples x {wl.nchan} "
+                        f"FP32 channels (point sources + noise) -> the {nt:,} pixel centres of "
+                        f"nside {nside} (RING), gauss1d FWHM 13.7', support 3 sigma"),
+                    contributions / (ms / 1e3), ms, "f32",
+                    {"samples": wl.nsamples, "targets": nt, "channels": wl.nchan,
+                     "nside": g.nside, "map_nside": nside, "pairs": pairs,
+                     "contributions": contributions, "contraction": "fp32"}, roof, cpu)
     out.update(extra)
     return out
 
@@ -458,7 +502,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cube",
-                    choices=["cube", "allsky", "batched", "sightlines"])
+                    choices=["cube", "allsky", "batched", "sightlines", "healpix"])
     ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "bf16", "fp16"],
                     help="contraction of the cube workload")
     ap.add_argument("--no-cpu", action="store_true")
@@ -468,9 +512,9 @@ def main():
                     help="only run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              f"(requested --gpus {a.gpus}); see DESIGN.md for how the path would shard.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              f"(requested --gpus {a.gpus}); the path would shard by target tiles or "
+              "channel blocks with no reduction.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -486,7 +530,7 @@ def main():
 
     dev = "cuda:0"
     run = {"cube": run_cube, "allsky": run_allsky, "batched": run_batched,
-           "sightlines": run_sightlines}[a.workload]
+           "sightlines": run_sightlines, "healpix": run_healpix}[a.workload]
     print(json.dumps(run(a, dev)), flush=True)
 
 

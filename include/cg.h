@@ -121,6 +121,22 @@ cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan);
 cg_status cg_create_sightlines(cg_gridder** out, const double* lon_deg, const double* lat_deg,
                                int64_t ntarget, int64_t nchan, void* stream);
 
+/* Pixel order of a HEALPix map (Gorski et al. 2005, the HEALPix paper the
+ * cited method builds on). */
+typedef enum cg_hpx_order { CG_HPX_RING = 0, CG_HPX_NESTED = 1 } cg_hpx_order;
+
+/* A full HEALPix map as the targets (Sect. 5: sight-line gridding onto the
+ * HEALPix pixel centres; App. A.1 grids to the nside = 512 map): a sight-line
+ * gridder whose 12 nside^2 targets are the pixel centres, target p being
+ * pixel p in `order` (cg_hpx_order).  The centres are computed on the device;
+ * internally 64 NESTED-consecutive pixels (an 8 x 8 block of one base face)
+ * form a tile.  Output order of get_datacube/get_weights is the pixel index
+ * in `order`.  nside: a power of two in [1, 8192].  Errors: CG_E_INVALID
+ * (bad order, nside or nchan), CG_E_OOM, CG_E_DEVICE.  Synchronises
+ * `stream`. */
+cg_status cg_create_healpix(cg_gridder** out, int64_t nside, int32_t order, int64_t nchan,
+                            void* stream);
+
 /* set_kernel(kernel_type, kernel_params, kernel_support, hpx_maxres)
  * (Listing 1, Sect. 3.5).  params: host double[nparams] (1 for GAUSS1D, 3
  * for GAUSS2D; sigmas in degrees, 0 < sigma_min <= sigma_maj, pa in
@@ -304,6 +320,12 @@ cg_status cg_hpx_ang2pix_ring(int64_t nside, int64_t n, const double* lon_deg, c
 /* Pixel centres: out_lon/out_lat degrees [n] of RING pixels pix[n]. */
 cg_status cg_hpx_pix2ang_ring(int64_t nside, int64_t n, const int64_t* pix, double* out_lon,
                               double* out_lat);
+/* Centres of pixels first .. first + count - 1 of an nside map in `order`
+ * (cg_hpx_order), the coordinates cg_create_healpix gives its targets:
+ * degrees into host arrays lon_deg/lat_deg [count].  nside a power of two in
+ * [1, 8192]; CG_E_INVALID for a range outside the map. */
+cg_status cg_hpx_centres(int64_t nside, int32_t order, int64_t first, int64_t count,
+                         double* lon_deg, double* lat_deg);
 /* Ring of each RING pixel: ring number (1-based) and position in the ring. */
 cg_status cg_hpx_pix2ring(int64_t nside, int64_t n, const int64_t* pix, int64_t* ring, int64_t* j);
 /* Ring table: for ring i (1..4 nside - 1): first index, pixel count, centre z. */

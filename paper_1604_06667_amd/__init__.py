@@ -7,6 +7,7 @@ paper's Listing 1: ``WcsGrid(header)`` / ``SlGrid(lon, lat)``,
 Torch supplies device memory and streams; every step runs in the HIP
 library.
 """
-from ._cg import (WcsGrid, SlGrid, Batch, CgError, lib, version, parse_header,  # noqa: F401
+from ._cg import (WcsGrid, SlGrid, HpxGrid, Batch, CgError, lib, version, parse_header,  # noqa: F401
                   hpx_ang2pix_ring, hpx_pix2ang_ring, hpx_pix2ring, hpx_ring_info,
-                  hpx_cap_ranges, hpx_targets_ranges, wcs_pix2world, PREC, KERNEL)
+                  hpx_cap_ranges, hpx_targets_ranges, hpx_centres, wcs_pix2world, PREC,
+                  KERNEL, HPX_ORDER)

@@ -47,6 +47,8 @@ _P = C.POINTER
 SIGNATURES = {
     "cg_create_wcs": (_i32, [_P(_vp), _P(CgWcs), _i64]),
     "cg_create_sightlines": (_i32, [_P(_vp), _vp, _vp, _i64, _i64, _vp]),
+    "cg_create_healpix": (_i32, [_P(_vp), _i64, _i32, _i64, _vp]),
+    "cg_hpx_centres": (_i32, [_i64, _i32, _i64, _i64, _vp, _vp]),
     "cg_set_kernel": (_i32, [_vp, _i32, _P(_d), _i32, _d, _d]),
     "cg_set_nside": (_i32, [_vp, _i64]),
     "cg_set_precision": (_i32, [_vp, _i32]),
@@ -343,6 +345,29 @@ class SlGrid(_Gridder):
         self.device = self.query(6)
 
 
+HPX_ORDER = {"ring": 0, "nested": 1}
+
+
+class HpxGrid(_Gridder):
+    """Gridder onto every pixel centre of a HEALPix map (cg_create_healpix):
+    12 nside^2 targets, target p being pixel p in ``order`` ("ring" or
+    "nested")."""
+
+    def __init__(self, nside: int, order: str = "ring", nchan: int = 1, stream=None):
+        super().__init__()
+        if order not in HPX_ORDER:
+            raise ValueError(f"order must be one of {sorted(HPX_ORDER)}")
+        self.nchan = int(nchan)
+        self.map_nside = int(nside)     # (nside is the lookup resolution)
+        self.map_order = order
+        h = C.c_void_p()
+        check(lib().cg_create_healpix(C.byref(h), self.map_nside, HPX_ORDER[order], self.nchan,
+                                      _stream(stream)))
+        self._h = h
+        self.out_shape = (12 * self.map_nside * self.map_nside,)
+        self.device = self.query(6)
+
+
 class Batch:
     """Many gridding jobs evaluated in one lookup pass and one persistent
     contraction launch (cg_batch_* of the C ABI).  ``gridders`` are WcsGrid /
@@ -459,6 +484,21 @@ def hpx_pix2ang_ring(nside, pix):
     lo = np.empty(p.shape[0])
     la = np.empty(p.shape[0])
     check(lib().cg_hpx_pix2ang_ring(int(nside), p.shape[0], _np_ptr(p), _np_ptr(lo), _np_ptr(la)))
+    return lo, la
+
+
+def hpx_centres(nside, order="ring", first=0, count=None):
+    """Pixel centres (degrees) of an nside map in ``order``, as the HpxGrid
+    targets get them (host code)."""
+    import numpy as np
+    if order not in HPX_ORDER:
+        raise ValueError(f"order must be one of {sorted(HPX_ORDER)}")
+    if count is None:
+        count = 12 * int(nside) ** 2 - int(first)
+    lo = np.empty(int(count))
+    la = np.empty(int(count))
+    check(lib().cg_hpx_centres(int(nside), HPX_ORDER[order], int(first), int(count),
+                               _np_ptr(lo), _np_ptr(la)))
     return lo, la
 
 

@@ -233,6 +233,66 @@ cg_status cg_create_sightlines(cg_gridder** out, const double* lon_deg, const do
   return CG_OK;
 }
 
+cg_status cg_create_healpix(cg_gridder** out, int64_t nside, int32_t order, int64_t nchan,
+                            void* stream) {
+  if (!out) return fail(CG_E_INVALID, "null pointer");
+  *out = nullptr;
+  if (order != CG_HPX_RING && order != CG_HPX_NESTED)
+    return fail(CG_E_INVALID, "unknown pixel order %d", order);
+  if (nside < 1 || nside > 8192 || (nside & (nside - 1)) != 0)
+    return fail(CG_E_INVALID, "nside must be a power of two in [1, 8192]");
+  if (nchan < 1 || nchan > 65535) return fail(CG_E_INVALID, "nchan must be in [1, 65535]");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t ntarget = cg::hpx::npix(nside);
+  cg_gridder* g = new cg_gridder();
+  (void)hipGetDevice(&g->device);
+  g->kind = 1;
+  g->ntarget = ntarget;
+  g->nchan = nchan;
+  g->ntiles = (ntarget + cg::kTile - 1) / cg::kTile;
+  g->nslots = g->ntiles * cg::kTile;
+  cg_status s = alloc_targets(g);
+  DevBuf lon, lat, ord;
+  if (s == CG_OK) {
+    hipError_t e = ensure(lon, sizeof(double) * ntarget);
+    if (e == hipSuccess) e = ensure(lat, sizeof(double) * ntarget);
+    if (e == hipSuccess) e = ensure(ord, sizeof(uint32_t) * ntarget);
+    if (e == hipSuccess)
+      e = cg::launch_hpx_centres(nside, order == CG_HPX_NESTED, lon.as<double>(), lat.as<double>(),
+                                 ord.as<uint32_t>(), st);
+    if (e == hipSuccess)
+      e = cg::launch_sl_targets(lon.as<double>(), lat.as<double>(), ord.as<uint32_t>(), ntarget,
+                                g->nslots, g->txyz.as<double>(), g->tll.as<double>(),
+                                g->slot_target.as<int32_t>(), g->target_slot.as<int32_t>(), st);
+    if (e == hipSuccess)
+      e = cg::launch_tile_caps(g->txyz.as<double>(), g->nslots, g->ntiles, g->caps.as<double>(),
+                               st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = hip_fail(e, "HEALPix target setup");
+  }
+  lon.release(); lat.release(); ord.release();
+  if (s != CG_OK) {
+    cg_destroy(g);
+    return s;
+  }
+  *out = g;
+  return CG_OK;
+}
+
+cg_status cg_hpx_centres(int64_t nside, int32_t order, int64_t first, int64_t count,
+                         double* lon_deg, double* lat_deg) {
+  if (order != CG_HPX_RING && order != CG_HPX_NESTED)
+    return fail(CG_E_INVALID, "unknown pixel order %d", order);
+  if (nside < 1 || nside > 8192 || (nside & (nside - 1)) != 0)
+    return fail(CG_E_INVALID, "nside must be a power of two in [1, 8192]");
+  if (count < 0 || first < 0 || first + count > cg::hpx::npix(nside))
+    return fail(CG_E_INVALID, "pixel range outside the map");
+  if (count > 0 && (!lon_deg || !lat_deg)) return fail(CG_E_INVALID, "null output pointer");
+  for (int64_t k = 0; k < count; ++k)
+    cg::hpx::pix_centre(nside, first + k, order == CG_HPX_NESTED, lon_deg + k, lat_deg + k);
+  return CG_OK;
+}
+
 cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params, int32_t nparams,
                         double support_deg, double hpx_maxres_deg) {
   if (!g) return fail(CG_E_INVALID, "null handle");

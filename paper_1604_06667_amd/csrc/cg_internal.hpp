@@ -158,6 +158,8 @@ hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st
 hipError_t launch_wcs_targets(const WcsDev& w, int64_t tile_w, int64_t tile_h, int64_t ntx,
                               int64_t nslots, double* txyz, double* tll, int32_t* slot_target,
                               int32_t* target_slot, hipStream_t st);
+hipError_t launch_hpx_centres(int64_t nside, int nested, double* lon, double* lat,
+                              uint32_t* order, hipStream_t st);
 hipError_t launch_sl_keys(const double* lon, const double* lat, int64_t n, uint32_t* keys,
                           uint32_t* vals, int* flag, hipStream_t st);
 hipError_t launch_sl_targets(const double* lon, const double* lat, const uint32_t* order,

@@ -145,6 +145,33 @@ hipError_t launch_sl_targets(const double* lon, const double* lat, const uint32_
   return hipGetLastError();
 }
 
+// Targets of a HEALPix map: target p is pixel p of the map's own order
+// (RING or NESTED), at its centre.  Slot s holds NESTED pixel s, so a tile
+// is 64 NESTED-consecutive pixels: an 8 x 8 block of one base face.
+// order[s] is the target index of slot s.
+__global__ void __launch_bounds__(256) k_hpx_centres(int64_t nside, int nested, int64_t n,
+                                                     double* __restrict__ lon,
+                                                     double* __restrict__ lat,
+                                                     uint32_t* __restrict__ order) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double a, d;
+  hpx::pix_centre(nside, p, nested != 0, &a, &d);
+  lon[p] = a;
+  lat[p] = d;
+  int64_t i, j;
+  hpx::nest2ring_ij(nside, p, &i, &j);
+  order[p] = (uint32_t)(nested ? p : hpx::ring_start(nside, i) + j);
+}
+
+hipError_t launch_hpx_centres(int64_t nside, int nested, double* lon, double* lat,
+                              uint32_t* order, hipStream_t st) {
+  const int64_t n = hpx::npix(nside);
+  hipLaunchKernelGGL(k_hpx_centres, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nside,
+                     nested, n, lon, lat, order);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Tile caps: centre = normalised sum of the tile's target vectors, radius =
 // largest angle from the centre to a target.  One wavefront per tile.

@@ -419,5 +419,79 @@ CG_HD int64_t ang2pix_nest(int64_t nside, double z, double st, double phi) {
   return face * nside * nside + (int64_t)(spread_bits((uint64_t)ix) | (spread_bits((uint64_t)iy) << 1));
 }
 
+// ---------------------------------------------------------------------------
+// Pixel centres as targets (a full HEALPix map gridded through the sight-line
+// path; the paper's App. A.1 grids onto the nside = 512 pixel centres).
+
+// Inverse of spread_bits: the even bits of v packed together.
+CG_HD uint64_t compact_bits(uint64_t v) {
+  v &= 0x5555555555555555ull;
+  v = (v | (v >> 1)) & 0x3333333333333333ull;
+  v = (v | (v >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  v = (v | (v >> 4)) & 0x00FF00FF00FF00FFull;
+  v = (v | (v >> 8)) & 0x0000FFFF0000FFFFull;
+  v = (v | (v >> 16)) & 0x00000000FFFFFFFFull;
+  return v;
+}
+
+// NESTED index -> (ring i, 0-based position j in the ring).  Pixel p lies in
+// base face f = p / nside^2 (face row f / 4: north, equator, south; column
+// f % 4) at in-face position (ix, iy), the even and odd bits of p mod
+// nside^2.  Its ring is (2 + row) nside - ix - iy - 1, and its position
+// along the ring, counted in half pixels from longitude 0, is
+// col2 nr + ix - iy + shift, where nr is the ring's pixel count / 4,
+// col2 = 2 col (+1 off the equatorial row) is the face centre's longitude
+// in units of pi / 4, and shift = 1 on rings whose first centre sits half
+// a pixel east of longitude 0 (Gorski et al. 2005, Sect. 4).
+CG_HD void nest2ring_ij(int64_t nside, int64_t p, int64_t* ring, int64_t* j) {
+  const int64_t nn = nside * nside;
+  const int64_t f = p / nn, loc = p - f * nn;
+  const int64_t ix = (int64_t)compact_bits((uint64_t)loc);
+  const int64_t iy = (int64_t)compact_bits((uint64_t)loc >> 1);
+  const int64_t row = f >> 2, col = f & 3;
+  const int64_t i = (2 + row) * nside - ix - iy - 1;
+  int64_t nr, kshift;
+  if (i < nside) { nr = i; kshift = 0; }
+  else if (i > 3 * nside) { nr = 4 * nside - i; kshift = 0; }
+  else { nr = nside; kshift = (i - nside) & 1; }
+  const int64_t col2 = 2 * col + ((row & 1) ? 0 : 1);
+  int64_t jp = (col2 * nr + ix - iy + 1 + kshift) / 2;   // 1-based
+  if (jp > 4 * nr) jp -= 4 * nr;
+  if (jp < 1) jp += 4 * nr;
+  *ring = i;
+  *j = jp - 1;
+}
+
+// Centre of pixel j (0-based) of ring i as (lon, lat) in degrees.  Cap rings
+// form 1 - |z| = i^2 / (3 nside^2) directly, so that latitudes next to the
+// poles keep full precision.
+CG_HD void ring_pixel_centre(int64_t nside, int64_t i, int64_t j, double* lon_deg,
+                             double* lat_deg) {
+  const double ns = (double)nside;
+  double z, st, phi;
+  if (i < nside || i > 3 * nside) {
+    const int64_t ic = i < nside ? i : 4 * nside - i;
+    const double omz = (double)(ic * ic) / (3.0 * ns * ns);
+    z = i < nside ? 1.0 - omz : omz - 1.0;
+    st = sqrt(omz * (2.0 - omz));
+    phi = ((double)j + 0.5) * kHalfPi / (double)ic;
+  } else {
+    z = (double)(2 * nside - i) * 2.0 / (3.0 * ns);
+    st = sqrt((1.0 - z) * (1.0 + z));
+    const double s = ((i - nside) & 1) ? 0.0 : 0.5;
+    phi = ((double)j + s) * kHalfPi / ns;
+  }
+  *lon_deg = phi * (180.0 / kPi);
+  *lat_deg = atan2(z, st) * (180.0 / kPi);
+}
+
+// Centre of pixel p of an nside map in RING (nested = false) or NESTED order.
+CG_HD void pix_centre(int64_t nside, int64_t p, bool nested, double* lon_deg, double* lat_deg) {
+  int64_t i, j;
+  if (nested) nest2ring_ij(nside, p, &i, &j);
+  else pix2ring(nside, p, &i, &j);
+  ring_pixel_centre(nside, i, j, lon_deg, lat_deg);
+}
+
 }  // namespace hpx
 }  // namespace cg

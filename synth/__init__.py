@@ -59,6 +59,8 @@ class Workload:
         t = self.target
         if t["kind"] == "wcs":
             return int(t["wcs"]["naxis1"]) * int(t["wcs"]["naxis2"])
+        if t["kind"] == "healpix":
+            return 12 * int(t["nside"]) ** 2
         return int(np.asarray(t["lon"]).shape[0])
 
 
@@ -342,6 +344,35 @@ def config4(njobs: int = 64, scale: float = 1.0, device="cpu") -> list[Workload]
                              {"kind": "wcs", "wcs": wcs}, kern, 3.0 * sig,
                              hpx_maxres=0.5 * q * sig if ell else 0.5 * sig))
     return jobs
+
+
+def config_hpx(nside: int = 512, oversample: float = 15.0, nchan: int = 2,
+               device="cpu") -> Workload:
+    """HEALPix-map gridding of App. A.1: samples uniform on the sphere,
+    ``oversample`` times as many as map pixels (15: ~47 M at nside 512);
+    channel 0 is 1024 random point sources seen through a Gaussian PSF of
+    FWHM 4 pixel sizes plus a smooth field, channel 1 unit Gaussian noise
+    (the paper grids signal and noise); kernel FWHM = PSF / 2 (13.7' at
+    nside 512), support 3 sigma, lookup resolution sigma / 2.  Targets: every
+    pixel centre of the nside map in RING order.
+    """
+    g = rng(6)
+    npix = 12 * nside * nside
+    n = int(round(oversample * npix))
+    lon, lat = uniform_sphere(g, n)
+    theta_pix = math.degrees(math.sqrt(4.0 * math.pi / npix))    # 6.87' at nside 512
+    fwhm_psf = 4.0 * theta_pix
+    sig = allsky_field(g, lon, lat, 1, 1024, fwhm_psf, device=device)
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(1604_6667_06)
+    noise = torch.randn((n, max(nchan - 1, 0)), generator=gen, device=device, dtype=torch.float32)
+    data = torch.cat([sig, noise], dim=1) if nchan > 1 else sig
+    sigma = 0.5 * fwhm_psf * FWHM_TO_SIGMA
+    return Workload(f"App.A.1 HEALPix map {n} -> nside {nside} ({npix} pixels) x {nchan}ch",
+                    lon, lat, data, "f32",
+                    {"kind": "healpix", "nside": int(nside), "order": "ring"},
+                    ("gauss1d", (sigma,)), 3.0 * sigma, hpx_maxres=0.5 * sigma)
 
 
 def config5(nsamples: int = 10_000_000, ntargets: int = 2_000_000, box: float = 30.0,

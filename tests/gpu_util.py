@@ -45,6 +45,8 @@ def make_gridder(wl: synth.Workload, prec="fp32", nside=None, dev="cuda:0"):
     import paper_1604_06667_amd as cgp
     if wl.target["kind"] == "wcs":
         g = cgp.WcsGrid(header_of(wl.target["wcs"], wl.nchan))
+    elif wl.target["kind"] == "healpix":
+        g = cgp.HpxGrid(wl.target["nside"], wl.target.get("order", "ring"), wl.nchan)
     else:
         tl = torch.as_tensor(np.asarray(wl.target["lon"], dtype=np.float64), device=dev)
         tb = torch.as_tensor(np.asarray(wl.target["lat"], dtype=np.float64), device=dev)

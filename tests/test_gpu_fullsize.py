@@ -7,6 +7,8 @@ benchmark times, on sampled outputs the FP64 oracle computes one by one.
   at both poles, across the 0/360 seam and at the +-180 deg grid edges;
 * sight lines (10,000,000 x 256 BF16 -> 2,000,000 targets, target-major
   cube): BF16, FP16 and FP32 paths on the targets of a 0.8x0.8 deg box;
+* HEALPix map (App. A.1: ~47 M samples x 2 -> the nside = 512 pixel
+  centres): FP32 path at both poles and across the seam;
 * batched (64 uneven jobs, tuned, replayed from the captured graph): the
   three largest jobs on central blocks.
 
@@ -152,6 +154,30 @@ def test_fullsize_sightlines():
         ev = _ev(cube.t(), wl, tidx, ref)
         say(f"  {prec} e_val={ev:.2e}")
         assert ev <= tol
+
+
+def test_fullsize_healpix_map():
+    # App. A.1: ~47 M uniform samples onto the nside = 512 map (FP32 path), at
+    # both poles and across the 0/360 seam on the equator
+    torch = _torch()
+    wl = synth.config_hpx(device="cuda:0")
+    say(f"full-size {wl.name}")
+    g = make_gridder(wl, "fp32")
+    lon, lat, d = to_device(wl)
+    counts, _ = g.neighbour_stats(lon, lat)
+    tl, tb = oracle.targets_of(wl)
+    seam = (np.abs(tb) < 0.5) & ((tl < 1.5) | (tl > 358.5))
+    blocks = [np.nonzero(tb > 88.5)[0], np.nonzero(tb < -88.5)[0], np.nonzero(seam)[0]]
+    cube, w = g.grid_datacube(lon, lat, d)
+    g.sync()
+    for tidx in blocks:
+        ref, sidx = _oracle_on(wl, tidx)
+        _check_counts(wl, counts, tidx, ref, sidx)
+        ev = _ev(cube, wl, tidx, ref)
+        ew = oracle.e_weights(w.reshape(-1)[torch.as_tensor(tidx, device=w.device)].cpu().numpy(),
+                              ref["W"])
+        say(f"  {tidx.size} pixels: fp32 e_val={ev:.2e} e_W={ew:.2e}")
+        assert ev <= TOL32 and ew <= TOL32
 
 
 def test_fullsize_batched_graph():

@@ -185,3 +185,37 @@ def test_targets_ranges_superset(nside, patch):
     npix_t = int((rng[:, 1] - rng[:, 0] + 1).sum())
     npix_c = int((cap[:, 1] - cap[:, 0] + 1).sum())
     assert npix_t <= npix_c
+
+
+# ---- HEALPix map targets (cg_hpx_centres: the code cg_create_healpix runs) ----
+
+@pytest.mark.parametrize("nside", [1, 2, 16, 256])
+@pytest.mark.parametrize("order", ["ring", "nested"])
+def test_map_centres_match_oracle(nside, order):
+    from oracle.healpix import centres
+    lo, la = cgp.hpx_centres(nside, order)
+    rlo, rla = centres(nside, order)
+    dl = np.abs((lo - rlo + 180.0) % 360.0 - 180.0)
+    assert dl.max() < 1e-9 and np.abs(la - rla).max() < 1e-9
+    assert lo.min() >= 0.0 and lo.max() < 360.0
+
+
+def test_map_centres_round_trip_and_ranges():
+    # RING centres map back to their own pixel; a sub-range equals the slice
+    nside = 64
+    lo, la = cgp.hpx_centres(nside, "ring")
+    assert np.array_equal(cgp.hpx_ang2pix_ring(nside, lo, la), np.arange(12 * nside * nside))
+    slo, sla = cgp.hpx_centres(nside, "nested", first=1000, count=77)
+    flo, fla = cgp.hpx_centres(nside, "nested")
+    assert np.array_equal(slo, flo[1000:1077]) and np.array_equal(sla, fla[1000:1077])
+
+
+@pytest.mark.parametrize("args", [(3, "ring"), (0, "ring"), (16384, "nested")])
+def test_map_centres_rejects_bad_nside(args):
+    with pytest.raises(cgp.CgError):
+        cgp.hpx_centres(*args, count=1)
+
+
+def test_map_centres_rejects_range_outside_map():
+    with pytest.raises(cgp.CgError):
+        cgp.hpx_centres(2, "ring", first=40, count=9)
