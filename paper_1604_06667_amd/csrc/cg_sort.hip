@@ -121,43 +121,59 @@ __global__ void __launch_bounds__(256) k_digit_scan(uint32_t* __restrict__ hist,
   if (t == 0) totals[blockIdx.x] = carry;
 }
 
+// Scatter of one block of kSortTile pairs.  The pairs are first ranked
+// stably by digit (ballots inside each wavefront, a prefix over wavefronts
+// per round) and placed in LDS in block-sorted order; the block then writes
+// them out in that order, so that each digit's run of the block goes to
+// consecutive global positions (whole segments instead of one scattered
+// 4-byte store per pair).
 template <bool JOB>
 __global__ void __launch_bounds__(kSortThreads) k_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int64_t nblocks,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* joff, int njobs) {
   constexpr int NW = kSortThreads / 64;
-  __shared__ uint32_t base[256];
+  __shared__ uint32_t gbase[256];     // global position of the block's first pair of digit d
+  __shared__ uint32_t lrun[256];      // pairs of digit d ranked so far, then local offsets
   __shared__ uint32_t wcnt[NW][256];
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];
   __shared__ int64_t s_off[JOB ? kMaxJobs + 1 : 1];
   const int t = threadIdx.x;
   stage_job_offsets<JOB>(s_off, joff, njobs);
   const int lane = t & 63;
   const int w = t >> 6;
-  // digit bases: exclusive scan of the 256 digit totals
   {
+    // digit bases: exclusive scan of the 256 digit totals
     const uint32_t v = totals[t];
-    base[t] = v;
+    gbase[t] = v;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-      const uint32_t u = t >= off ? base[t - off] : 0u;
+      const uint32_t u = t >= off ? gbase[t - off] : 0u;
       __syncthreads();
-      base[t] += u;
+      gbase[t] += u;
       __syncthreads();
     }
-    const uint32_t excl = base[t] - v;
+    const uint32_t excl = gbase[t] - v;
     __syncthreads();
-    base[t] = excl + hist[(int64_t)t * nblocks + blockIdx.x];
+    gbase[t] = excl + hist[(int64_t)t * nblocks + blockIdx.x];
+    lrun[t] = 0u;
   }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t blk = (int64_t)blockIdx.x * kSortTile;
+  uint32_t key[kSortItems], val[kSortItems], dig[kSortItems], lpos[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = blk + (int64_t)r * kSortThreads + t;
     const bool valid = i < n;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = valid ? sort_digit<JOB>(key, val, shift, s_off, njobs) : 0u;
-    // lanes holding the same digit
+    key[r] = valid ? kin[i] : 0u;
+    val[r] = valid ? vin[i] : 0u;
+  }
+  // ranking: round r holds the pairs blk + r * kSortThreads + (0 .. kSortThreads - 1)
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = blk + (int64_t)r * kSortThreads + t < n;
+    const uint32_t d = valid ? sort_digit<JOB>(key[r], val[r], shift, s_off, njobs) : 0u;
+    dig[r] = d;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -171,23 +187,50 @@ __global__ void __launch_bounds__(kSortThreads) k_scatter(
     if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     {
-      // digit t: exclusive prefix over wavefronts on top of the running base
-      uint32_t run = base[t];
+      uint32_t run = lrun[t];
 #pragma unroll
       for (int q = 0; q < NW; ++q) {
         const uint32_t c = wcnt[q][t];
         wcnt[q][t] = run;
         run += c;
       }
-      base[t] = run;
+      lrun[t] = run;
     }
     __syncthreads();
-    if (valid) {
-      const uint32_t pos = wcnt[w][d] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
-    }
+    lpos[r] = wcnt[w][d] + rank;
     __syncthreads();
+  }
+  // local offsets: exclusive scan of the block's digit counts
+  {
+    const uint32_t v = lrun[t];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t u = t >= off ? lrun[t - off] : 0u;
+      __syncthreads();
+      lrun[t] += u;
+      __syncthreads();
+    }
+    const uint32_t excl = lrun[t] - v;
+    __syncthreads();
+    lrun[t] = excl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (blk + (int64_t)r * kSortThreads + t < n) {
+      const uint32_t p = lrun[dig[r]] + lpos[r];
+      sk[p] = key[r];
+      sv[p] = val[r];
+    }
+  }
+  __syncthreads();
+  const int nb = (int)((n - blk) < (int64_t)kSortTile ? (n - blk) : (int64_t)kSortTile);
+  for (int j = t; j < nb; j += kSortThreads) {
+    const uint32_t k = sk[j], v = sv[j];
+    const uint32_t d = sort_digit<JOB>(k, v, shift, s_off, njobs);
+    const uint32_t pos = gbase[d] + ((uint32_t)j - lrun[d]);
+    kout[pos] = k;
+    vout[pos] = v;
   }
 }
 
