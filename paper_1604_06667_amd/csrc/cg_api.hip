@@ -21,8 +21,10 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
   CG_HIP(ensure(g->ring_off, sizeof(uint32_t) * (4 * nside + 1)), "alloc ring offsets");
   CG_HIP(ensure(g->sx, sizeof(double) * 3 * n), "alloc sorted vectors");
   if (with_data) CG_HIP(ensure(g->sdata, sizeof(float) * n * g->nchan), "alloc sorted data");
+  CG_HIP(ensure(g->rec, 4 * sizeof(double) * n), "alloc sample records");
+  const int npack = with_data && g->nchan <= 2 ? (int)g->nchan : 0;
   CG_HIP(cg::launch_prep(lon, lat, n, nside, g->keys.as<uint32_t>(), g->vals.as<uint32_t>(),
-                         g->flag.as<int>(), st),
+                         g->flag.as<int>(), g->rec.as<double>(), data, dtype, ld, npack, st),
          "prep");
   bool in_tmp = false;
   const int bits = bits_for((uint64_t)cg::hpx::npix(nside));
@@ -33,8 +35,9 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
   g->sorted_vals = in_tmp ? g->vals2.as<uint32_t>() : g->vals.as<uint32_t>();
   uint32_t* roff = g->ring_off.as<uint32_t>();
   CG_HIP(cg::launch_ring_offsets(g->sorted_keys, n, nside, roff, st), "ring offsets");
-  CG_HIP(cg::launch_permute(g->sorted_vals, roff + 4 * nside, n, lon, lat, data, dtype, ld,
-                            g->nchan, with_data, n, g->sx.as<double>(), g->sdata.as<float>(), st),
+  CG_HIP(cg::launch_permute(g->sorted_vals, roff + 4 * nside, n, g->rec.as<double>(), data, dtype,
+                            ld, g->nchan, with_data, npack, n, g->sx.as<double>(),
+                            g->sdata.as<float>(), st),
          "permute");
   CG_HIP(cg::launch_tile_ranges(g->ntiles, g->ring_first.as<int32_t>(),
                                 g->range_off.as<uint64_t>(), g->win.as<uint32_t>(),

@@ -142,16 +142,18 @@ __device__ __forceinline__ float pair_weight(const KernelParams& kp, double c2, 
 // ---------------------------------------------------------------- launchers
 // All launches are asynchronous on `st`; return hipSuccess or the launch error.
 
+// rec: 4 doubles per sample (unit vector; channels 0-1 as FP32 when npack > 0)
 hipError_t launch_prep(const double* lon, const double* lat, int64_t n, int64_t nside,
-                       uint32_t* keys, uint32_t* vals, int* flag, hipStream_t st);
+                       uint32_t* keys, uint32_t* vals, int* flag, double* rec, const void* data,
+                       int dtype, int64_t ld, int npack, hipStream_t st);
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                       uint32_t* hist, int64_t n, int bits, bool* result_in_tmp, hipStream_t st);
 size_t radix_hist_elems(int64_t n);   // includes 256 digit totals
 hipError_t launch_ring_offsets(const uint32_t* keys, int64_t n, int64_t nside, uint32_t* ring_off,
                                hipStream_t st);
 hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int64_t n,
-                          const double* lon, const double* lat, const void* data, int dtype,
-                          int64_t ld, int64_t nchan, bool with_data, int64_t cap, double* sx,
+                          const double* rec, const void* data, int dtype, int64_t ld,
+                          int64_t nchan, bool with_data, int npack, int64_t cap, double* sx,
                           float* sdata, hipStream_t st);
 hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st);
 

@@ -13,15 +13,38 @@ namespace cg {
 // prep: RING key per sample; invalid coordinates get the sentinel key Npix
 // (sorted past every ring) and raise the sticky input flag.
 
+template <typename T>
+__device__ __forceinline__ float to_f32(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ float to_f32<double>(const double* p, int64_t i) { return (float)p[i]; }
+template <>
+__device__ __forceinline__ float to_f32<float>(const float* p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float to_f32<uint16_t>(const uint16_t* p, int64_t i) {
+  return __uint_as_float(((uint32_t)p[i]) << 16);   // bfloat16 -> float (exact)
+}
+template <>
+__device__ __forceinline__ float to_f32<_Float16>(const _Float16* p, int64_t i) { return (float)p[i]; }
+
+// HEALPix RING key and value (the sample's own index) of every sample, and
+// its record in input order: the unit vector and, when the cube has at most
+// two channels, the channels as FP32 in the fourth word.  The permutation
+// after the sort then reads one 32-byte record per sample instead of the
+// separate longitude, latitude and data rows.
+template <typename T>
 __global__ void __launch_bounds__(256) k_prep(const double* __restrict__ lon,
                                               const double* __restrict__ lat, int64_t n,
                                               int64_t nside, uint32_t* __restrict__ keys,
-                                              uint32_t* __restrict__ vals, int* flag) {
+                                              uint32_t* __restrict__ vals, int* flag,
+                                              double4* __restrict__ rec,
+                                              const T* __restrict__ data, int64_t ld, int npack) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double a = lon[i];
   const double d = lat[i];
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
   uint32_t key;
+  double4 r = make_double4(nan, nan, nan, 0.0);
   if (!(isfinite(a) && isfinite(d) && fabs(d) <= 90.0)) {
     key = (uint32_t)hpx::npix(nside);
     atomicOr(flag, 1);
@@ -29,20 +52,49 @@ __global__ void __launch_bounds__(256) k_prep(const double* __restrict__ lon,
     double am = fmod(a, 360.0);
     if (am < 0.0) am += 360.0;
     const double phi = am * (hpx::kPi / 180.0);
-    double sd, cd;
+    double sd, cd, sa, ca;
     sincos(d * (hpx::kPi / 180.0), &sd, &cd);
+    sincos(phi, &sa, &ca);
     key = (uint32_t)hpx::ang2pix_ring(nside, sd, cd, phi);
+    r.x = cd * ca;
+    r.y = cd * sa;
+    r.z = sd;
+  }
+  if (npack > 0) {
+    const float d0 = to_f32<T>(data, i * ld);
+    const float d1 = npack > 1 ? to_f32<T>(data, i * ld + 1) : 0.0f;
+    r.w = __longlong_as_double((long long)(((uint64_t)__float_as_uint(d1) << 32) |
+                                           (uint64_t)__float_as_uint(d0)));
   }
   keys[i] = key;
   vals[i] = (uint32_t)i;
+  rec[i] = r;
 }
 
 hipError_t launch_prep(const double* lon, const double* lat, int64_t n, int64_t nside,
-                       uint32_t* keys, uint32_t* vals, int* flag, hipStream_t st) {
+                       uint32_t* keys, uint32_t* vals, int* flag, double* rec, const void* data,
+                       int dtype, int64_t ld, int npack, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, st, lon, lat, n, nside, keys,
-                     vals, flag);
+  const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+  double4* r = reinterpret_cast<double4*>(rec);
+  switch (dtype) {
+    case 0:
+      hipLaunchKernelGGL(k_prep<double>, grid, blk, 0, st, lon, lat, n, nside, keys, vals, flag, r,
+                         (const double*)data, ld, npack);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_prep<float>, grid, blk, 0, st, lon, lat, n, nside, keys, vals, flag, r,
+                         (const float*)data, ld, npack);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_prep<_Float16>, grid, blk, 0, st, lon, lat, n, nside, keys, vals, flag,
+                         r, (const _Float16*)data, ld, npack);
+      break;
+    default:
+      hipLaunchKernelGGL(k_prep<uint16_t>, grid, blk, 0, st, lon, lat, n, nside, keys, vals, flag,
+                         r, (const uint16_t*)data, ld, npack);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -424,41 +476,29 @@ hipError_t launch_ring_offsets(const uint32_t* keys, int64_t n, int64_t nside, u
 // permute: sorted unit vectors (SoA) and, for narrow cubes, the data rows in
 // sorted order converted to FP32 (so the gather streams contiguous rows).
 
-template <typename T>
-__device__ __forceinline__ float to_f32(const T* p, int64_t i);
-template <>
-__device__ __forceinline__ float to_f32<double>(const double* p, int64_t i) { return (float)p[i]; }
-template <>
-__device__ __forceinline__ float to_f32<float>(const float* p, int64_t i) { return p[i]; }
-template <>
-__device__ __forceinline__ float to_f32<uint16_t>(const uint16_t* p, int64_t i) {
-  return __uint_as_float(((uint32_t)p[i]) << 16);   // bfloat16 -> float (exact)
-}
-template <>
-__device__ __forceinline__ float to_f32<_Float16>(const _Float16* p, int64_t i) { return (float)p[i]; }
-
 template <typename T, bool VEC4>
 __global__ void __launch_bounds__(256) k_permute(const uint32_t* __restrict__ vals,
                                                  const uint32_t* __restrict__ nvalid_p,
-                                                 const double* __restrict__ lon,
-                                                 const double* __restrict__ lat,
+                                                 const double4* __restrict__ rec,
                                                  const T* __restrict__ data, int64_t ld,
-                                                 int64_t nchan, int with_data, int64_t cap,
-                                                 double* __restrict__ sx, float* __restrict__ sdata) {
+                                                 int64_t nchan, int with_data, int npack,
+                                                 int64_t cap, double* __restrict__ sx,
+                                                 float* __restrict__ sdata) {
   const int64_t nvalid = (int64_t)(*nvalid_p);
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nvalid) return;
   const int64_t src = vals[p];
-  double am = fmod(lon[src], 360.0);
-  if (am < 0.0) am += 360.0;
-  double sa, ca, sd, cd;
-  sincos(am * (hpx::kPi / 180.0), &sa, &ca);
-  sincos(lat[src] * (hpx::kPi / 180.0), &sd, &cd);
-  sx[p] = cd * ca;
-  sx[cap + p] = cd * sa;
-  sx[2 * cap + p] = sd;
+  const double4 r = rec[src];
+  sx[p] = r.x;
+  sx[cap + p] = r.y;
+  sx[2 * cap + p] = r.z;
   if (with_data) {
-    if constexpr (VEC4) {
+    if (npack > 0) {
+      // channels carried in the record
+      const uint64_t b = (uint64_t)__double_as_longlong(r.w);
+      sdata[p * nchan] = __uint_as_float((uint32_t)b);
+      if (npack > 1) sdata[p * nchan + 1] = __uint_as_float((uint32_t)(b >> 32));
+    } else if constexpr (VEC4) {
       // FP32 rows with nchan and ld multiples of 4 and 16-byte aligned: whole
       // 16-byte pieces per load and store
       const float4* in = reinterpret_cast<const float4*>(data + src * ld);
@@ -471,34 +511,35 @@ __global__ void __launch_bounds__(256) k_permute(const uint32_t* __restrict__ va
 }
 
 hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int64_t n,
-                          const double* lon, const double* lat, const void* data, int dtype,
-                          int64_t ld, int64_t nchan, bool with_data, int64_t cap, double* sx,
+                          const double* rec, const void* data, int dtype, int64_t ld,
+                          int64_t nchan, bool with_data, int npack, int64_t cap, double* sx,
                           float* sdata, hipStream_t st) {
   // nvalid_dev points at the number of valid samples (ring_off[4 nside]);
   // the grid covers all n sorted entries and threads past it return.
   if (n <= 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
   const int wd = with_data ? 1 : 0;
+  const double4* r = reinterpret_cast<const double4*>(rec);
   switch (dtype) {
     case 0:
-      hipLaunchKernelGGL((k_permute<double, false>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
-                         (const double*)data, ld, nchan, wd, cap, sx, sdata);
+      hipLaunchKernelGGL((k_permute<double, false>), grid, blk, 0, st, vals, nvalid_dev, r,
+                         (const double*)data, ld, nchan, wd, npack, cap, sx, sdata);
       break;
     case 1:
       if (wd && nchan % 4 == 0 && ld % 4 == 0 && ((uintptr_t)data & 15) == 0)
-        hipLaunchKernelGGL((k_permute<float, true>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
-                           (const float*)data, ld, nchan, wd, cap, sx, sdata);
+        hipLaunchKernelGGL((k_permute<float, true>), grid, blk, 0, st, vals, nvalid_dev, r,
+                           (const float*)data, ld, nchan, wd, npack, cap, sx, sdata);
       else
-        hipLaunchKernelGGL((k_permute<float, false>), grid, blk, 0, st, vals, nvalid_dev, lon,
-                           lat, (const float*)data, ld, nchan, wd, cap, sx, sdata);
+        hipLaunchKernelGGL((k_permute<float, false>), grid, blk, 0, st, vals, nvalid_dev, r,
+                           (const float*)data, ld, nchan, wd, npack, cap, sx, sdata);
       break;
     case 2:
-      hipLaunchKernelGGL((k_permute<_Float16, false>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
-                         (const _Float16*)data, ld, nchan, wd, cap, sx, sdata);
+      hipLaunchKernelGGL((k_permute<_Float16, false>), grid, blk, 0, st, vals, nvalid_dev, r,
+                         (const _Float16*)data, ld, nchan, wd, npack, cap, sx, sdata);
       break;
     default:
-      hipLaunchKernelGGL((k_permute<uint16_t, false>), grid, blk, 0, st, vals, nvalid_dev, lon, lat,
-                         (const uint16_t*)data, ld, nchan, wd, cap, sx, sdata);
+      hipLaunchKernelGGL((k_permute<uint16_t, false>), grid, blk, 0, st, vals, nvalid_dev, r,
+                         (const uint16_t*)data, ld, nchan, wd, npack, cap, sx, sdata);
       break;
   }
   return hipGetLastError();
