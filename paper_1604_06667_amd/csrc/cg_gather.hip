@@ -71,6 +71,7 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   double wacc = 0.0;
   const uint64_t c0 = tv.cand_off[tile], c1 = tv.cand_off[tile + 1];
   const int64_t cap = tv.ncap;
+  const double thr = 1.0 - 0.5 * kp.cs2 - 2e-15;
   for (uint64_t base = c0; base < c1; base += kChunk) {
     const int kmax = (int)((c1 - base) < (uint64_t)kChunk ? (c1 - base) : (uint64_t)kChunk);
     if (lane < kmax) {
@@ -83,12 +84,24 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
         if (c < nchan) s_d[lane * CMAX + c] = sdata[pos * nchan + c];
     }
     __syncthreads();
-    // candidates of the chunk within the support of this lane's target
+    // candidates of the chunk that may lie within the support of this lane's
+    // target: p_n . p_t >= 1 - cs2/2 (the same cut, as |p_n - p_t|^2 =
+    // 2 - 2 p_n . p_t for unit vectors) loosened by 2e-15, which covers the
+    // few-ulp deviation of the rounded vectors from unit length and the
+    // rounding of the dot product, so the marked set is a superset.  The
+    // exact FP64 chord test below decides every marked pair.
     uint64_t inside = 0;
-    for (int k = 0; k < kmax; ++k) {
-      const double dx = s_x[k] - tx, dy = s_y[k] - ty, dz = s_z[k] - tz;
-      const double c2 = dx * dx + dy * dy + dz * dz;
-      if (c2 <= kp.cs2) inside |= 1ull << k;
+    if (kmax == kChunk) {
+#pragma unroll
+      for (int k = kChunk - 1; k >= 0; --k) {
+        const double dot = fma(s_x[k], tx, fma(s_y[k], ty, s_z[k] * tz));
+        inside = (inside << 1) | (uint64_t)(dot >= thr);
+      }
+    } else {
+      for (int k = kmax - 1; k >= 0; --k) {
+        const double dot = fma(s_x[k], tx, fma(s_y[k], ty, s_z[k] * tz));
+        inside = (inside << 1) | (uint64_t)(dot >= thr);
+      }
     }
     float p[CMAX];
 #pragma unroll
@@ -99,7 +112,9 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
       inside &= inside - 1;
       const double dx = s_x[k] - tx, dy = s_y[k] - ty, dz = s_z[k] - tz;
       const double c2 = dx * dx + dy * dy + dz * dz;
-      const float w = pair_weight(kp, c2, dx, dy, dz, ax[0], ax[1], ax[2], bx[0], bx[1], bx[2]);
+      const float w = c2 <= kp.cs2 ? pair_weight(kp, c2, dx, dy, dz, ax[0], ax[1], ax[2], bx[0],
+                                                 bx[1], bx[2])
+                                   : 0.0f;
       pw += w;
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
