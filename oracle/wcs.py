@@ -1,8 +1,9 @@
 """FITS-WCS pixel -> world for the oracle (test infrastructure).
 
 Written from the FITS WCS papers cited in the paper's introduction
-(Greisen & Calabretta 2002; Calabretta & Greisen 2002), for the two
-projections the benchmark grids use:
+(Greisen & Calabretta 2002; Calabretta & Greisen 2002), for the
+projections the benchmark grids use and two more the paper names (SFL in
+Listing 1, ZEA in Fig. 1):
 
 * CAR, non-oblique (CRVAL2 = 0): the plate carree, lon = CRVAL1 + x,
   lat = y with intermediate coordinates x = CDELT1 (i - CRPIX1),
@@ -15,6 +16,12 @@ projections the benchmark grids use:
   native-to-celestial rotation with (alpha_p, delta_p) = (CRVAL1, CRVAL2)
   and phi_p = 180 deg.  Pixels with R > 1 lie outside the projection and
   have no world coordinate (NaN).
+* ZEA (zenithal equal-area): as SIN but R = 2 sin((90 deg - theta) / 2)
+  (radians), i.e. theta = 90 deg - 2 asin(R / 2); R > 2 has no world
+  coordinate.
+* SFL (Sanson-Flamsteed), non-oblique (CRVAL2 = 0) like CAR: x = phi cos
+  theta, y = theta, so lat = y and lon = CRVAL1 + x / cos(y); points with
+  |y| > 90 deg or |x / cos y| > 180 deg lie outside the projection.
 
 (i, j) are FITS 1-based pixel indices along NAXIS1 / NAXIS2.
 """
@@ -39,11 +46,24 @@ def wcs_world(wcs: dict, i, j):
         lon = np.where(bad, np.nan, lon)
         lat = np.where(bad, np.nan, lat)
         return lon, lat
-    if proj == "SIN":
+    if proj == "SFL":
+        if wcs.get("crval2", 0.0) != 0.0:
+            raise ValueError("oblique SFL (CRVAL2 != 0) is not supported")
+        lat = y.copy()
+        with np.errstate(invalid="ignore", divide="ignore"):
+            dlon = x / np.cos(np.radians(lat))
+        dlon = np.where(x == 0.0, 0.0, dlon)
+        bad = (np.abs(lat) > 90.0) | ~(np.abs(dlon) <= 180.0)
+        lon = np.mod(wcs["crval1"] + dlon, 360.0)
+        return np.where(bad, np.nan, lon), np.where(bad, np.nan, lat)
+    if proj in ("SIN", "ZEA"):
         r = np.radians(np.hypot(x, y))
         phi = np.arctan2(np.radians(x), -np.radians(y))
         with np.errstate(invalid="ignore"):
-            theta = np.arccos(r)              # NaN outside the disc R > 1
+            if proj == "SIN":
+                theta = np.arccos(r)          # NaN outside the disc R > 1
+            else:
+                theta = np.pi / 2 - 2.0 * np.arcsin(r / 2.0)   # NaN for R > 2
         ap = np.radians(wcs["crval1"])
         dp = np.radians(wcs["crval2"])
         php = np.pi                           # LONPOLE = 180 deg for zenithal

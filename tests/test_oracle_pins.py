@@ -160,6 +160,62 @@ def test_sin_closed_forms(crval2):
     np.testing.assert_allclose(np.angle(np.exp(1j * (pa[ok] - np.arctan2(x[ok], y[ok])))), 0, atol=1e-10)
 
 
+@pytest.mark.parametrize("crval2", [0.0, 41.0, -80.0])
+def test_zea_closed_forms(crval2):
+    # zenithal equal-area: a pixel at projection radius R (radians) lies
+    # 2 asin(R/2) from the reference point, in position angle atan2(x, y);
+    # the cell spacing 1.2 deg reaches 84 deg from the reference
+    w = dict(_sin_hdr(crval2), proj="ZEA", cdelt1=-1.2, cdelt2=1.2)
+    lon, lat = wcs_world(w, [51.0], [51.0])
+    assert lon[0] == pytest.approx(120.0, abs=1e-12) and lat[0] == pytest.approx(crval2, abs=1e-12)
+    ii, jj = np.meshgrid(np.arange(1, 102, 5), np.arange(1, 102, 5))
+    lon, lat = wcs_world(w, ii.ravel(), jj.ravel())
+    x = -1.2 * (ii.ravel() - 51.0)
+    y = 1.2 * (jj.ravel() - 51.0)
+    R = np.radians(np.hypot(x, y))
+    ok = R <= 2.0
+    assert np.all(np.isfinite(lat[ok])) and np.all(np.isnan(lat[~ok]))
+    p = unit_vectors(lon[ok], lat[ok])
+    c = unit_vectors([120.0], [crval2])[0]
+    dist = np.arctan2(np.linalg.norm(np.cross(p, c), axis=1), p @ c)
+    np.testing.assert_allclose(dist, 2 * np.arcsin(R[ok] / 2), rtol=1e-12, atol=1e-14)
+    e = np.array([-math.sin(math.radians(120)), math.cos(math.radians(120)), 0.0])
+    nvec = np.cross(c, e)
+    pa = np.arctan2(p @ e, p @ nvec)
+    m = (R[ok] > 1e-6) & (R[ok] < 1.9)
+    d = np.angle(np.exp(1j * (pa[m] - np.arctan2(x[ok][m], y[ok][m]))))
+    np.testing.assert_allclose(d, 0, atol=1e-9)
+
+
+def test_zea_equal_area():
+    # equal-area: the share of a large uniform pixel grid inside a cap of
+    # angular radius rho around the reference is the cap's solid angle over
+    # the projected area per pixel (2 pi (1 - cos rho) / cdelt^2)
+    w = {"proj": "ZEA", "naxis1": 801, "naxis2": 801, "crpix1": 401.0, "crpix2": 401.0,
+         "crval1": 10.0, "crval2": 20.0, "cdelt1": -0.05, "cdelt2": 0.05}
+    lon, lat = wcs_targets(w)
+    p = unit_vectors(lon, lat)
+    c = unit_vectors([10.0], [20.0])[0]
+    for rho in (5.0, 15.0):
+        n = np.sum(p @ c >= math.cos(math.radians(rho)))
+        expect = 2 * math.pi * (1 - math.cos(math.radians(rho))) / math.radians(0.05) ** 2
+        assert abs(n - expect) < 4 * math.sqrt(expect) + 0.02 * expect
+
+
+def test_sfl_closed_forms():
+    # Sanson-Flamsteed: parallels are straight and true to scale, the
+    # central meridian and the equator are true to scale
+    w = {"proj": "SFL", "naxis1": 361, "naxis2": 181, "crpix1": 181.0, "crpix2": 91.0,
+         "crval1": 30.0, "crval2": 0.0, "cdelt1": -1.0, "cdelt2": 1.0}
+    lon, lat = wcs_world(w, [181.0, 181.0, 151.0, 151.0, 181.0], [91.0, 151.0, 91.0, 151.0, 181.0])
+    np.testing.assert_allclose(lat, [0.0, 60.0, 0.0, 60.0, 90.0], atol=1e-12)
+    # x = +30 deg (east) on the equator is 30 deg east; at lat 60 it is 60 deg east
+    np.testing.assert_allclose(lon[:4], [30.0, 30.0, 60.0, 90.0], atol=1e-12)
+    # outside the projection: beyond 180 deg of longitude at lat 60
+    lo, la = wcs_world(w, [181.0 - 100.0], [151.0])
+    assert np.isnan(lo[0]) and np.isnan(la[0])
+
+
 def test_sin_equatorial_row_and_column():
     w = _sin_hdr(0.0)
     k = np.arange(1, 40)
