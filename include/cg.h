@@ -88,11 +88,15 @@ typedef enum cg_kernel_type {
                       axis, east of north, at the target */
 } cg_kernel_type;
 
-typedef enum cg_proj { CG_PROJ_CAR = 0, CG_PROJ_SIN = 1 } cg_proj;
+/* FITS/WCS projections (Calabretta & Greisen 2002): CAR and SFL
+ * (Sanson-Flamsteed, Listing 1) non-oblique; SIN and ZEA (zenithal
+ * equal-area, Fig. 1) zenithal with LONPOLE = 180 deg. */
+typedef enum cg_proj { CG_PROJ_CAR = 0, CG_PROJ_SIN = 1, CG_PROJ_SFL = 2, CG_PROJ_ZEA = 3 } cg_proj;
 
 /* Target grid of a WcsGrid: the subset of a FITS/WCS header that defines the
- * pixel centres (Listing 1).  CAR requires crval2 == 0 (non-oblique);
- * SIN uses LONPOLE = 180 deg.  Pixel (i, j) is 1-based along NAXIS1/NAXIS2. */
+ * pixel centres (Listing 1).  CAR and SFL require crval2 == 0
+ * (non-oblique); SIN and ZEA use LONPOLE = 180 deg.  Pixel (i, j) is 1-based
+ * along NAXIS1/NAXIS2. */
 typedef struct cg_wcs {
   int32_t proj;          /* cg_proj */
   int32_t reserved;      /* must be 0 */
@@ -109,7 +113,9 @@ typedef struct cg_gridder cg_gridder;   /* opaque handle */
  * HIP device.  The handle owns its accumulators (S: nchan x targets FP32,
  * W: FP64); they start empty.  Errors: CG_E_INVALID (null pointer, naxis <
  * 1, nchan < 1, zero cdelt), CG_E_UNSUPPORTED (unknown projection, oblique
- * CAR), CG_E_OOM, CG_E_DEVICE.  Synchronises the null stream once. */
+ * CAR or SFL), CG_E_OOM, CG_E_DEVICE.  Pixels without a world coordinate
+ * (outside the projection) are empty targets.  Synchronises the null stream
+ * once. */
 cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan);
 
 /* SlGrid(lon, lat) (Sect. 3.5, 5): a gridder whose targets are `ntarget`

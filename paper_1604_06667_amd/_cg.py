@@ -17,7 +17,7 @@ OK, E_INVALID, E_STATE, E_OOM, E_UNSUPPORTED, E_DEVICE, E_INPUT = 0, -1, -2, -3,
 F64, F32, F16, BF16 = 0, 1, 2, 3
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 KERNEL = {"gauss1d": 0, "gauss2d": 1}
-PROJ = {"CAR": 0, "SIN": 1}
+PROJ = {"CAR": 0, "SIN": 1, "SFL": 2, "ZEA": 3}
 LAYOUT = {"channel": 0, "target": 1}
 
 
@@ -163,7 +163,7 @@ def parse_header(header: dict):
     ctype = str(h.get("CTYPE1", "RA---CAR")).upper()
     proj = ctype[-3:]
     if proj not in PROJ:
-        raise CgError(E_UNSUPPORTED, f"projection {proj!r} is not supported (CAR, SIN)")
+        raise CgError(E_UNSUPPORTED, f"projection {proj!r} is not supported (CAR, SIN, SFL, ZEA)")
     w = CgWcs(PROJ[proj], 0, int(h["NAXIS1"]), int(h["NAXIS2"]),
               float(h.get("CRPIX1", 1.0)), float(h.get("CRPIX2", 1.0)),
               float(h.get("CRVAL1", 0.0)), float(h.get("CRVAL2", 0.0)),
@@ -315,7 +315,7 @@ class _Gridder:
 
 
 class WcsGrid(_Gridder):
-    """Gridder onto the pixel centres of a FITS/WCS header (CAR or SIN)."""
+    """Gridder onto the pixel centres of a FITS/WCS header (CAR, SIN, SFL or ZEA)."""
 
     def __init__(self, header: dict, nchan: int | None = None):
         super().__init__()

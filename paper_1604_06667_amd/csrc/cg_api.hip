@@ -133,7 +133,8 @@ const char* cg_version(void) { return "cg 0.1 (gfx950)"; }
 cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan) {
   if (!out || !wcs) return fail(CG_E_INVALID, "null pointer");
   *out = nullptr;
-  if (wcs->proj != CG_PROJ_CAR && wcs->proj != CG_PROJ_SIN)
+  if (wcs->proj != CG_PROJ_CAR && wcs->proj != CG_PROJ_SIN && wcs->proj != CG_PROJ_SFL &&
+      wcs->proj != CG_PROJ_ZEA)
     return fail(CG_E_UNSUPPORTED, "unknown projection %d", wcs->proj);
   if (wcs->reserved != 0) return fail(CG_E_INVALID, "reserved field must be 0");
   if (wcs->naxis1 < 1 || wcs->naxis2 < 1) return fail(CG_E_INVALID, "naxis must be >= 1");
@@ -142,8 +143,9 @@ cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan) {
         isfinite(wcs->cdelt2) && isfinite(wcs->crpix1) && isfinite(wcs->crpix2) &&
         isfinite(wcs->crval1) && isfinite(wcs->crval2)))
     return fail(CG_E_INVALID, "WCS keywords must be finite with non-zero CDELT");
-  if (wcs->proj == CG_PROJ_CAR && wcs->crval2 != 0.0)
-    return fail(CG_E_UNSUPPORTED, "oblique CAR (CRVAL2 != 0) is not supported");
+  if ((wcs->proj == CG_PROJ_CAR || wcs->proj == CG_PROJ_SFL) && wcs->crval2 != 0.0)
+    return fail(CG_E_UNSUPPORTED, "oblique %s (CRVAL2 != 0) is not supported",
+                wcs->proj == CG_PROJ_CAR ? "CAR" : "SFL");
   if (fabs(wcs->crval2) > 90.0) return fail(CG_E_INVALID, "|CRVAL2| > 90");
   const int64_t nt = wcs->naxis1 * wcs->naxis2;
   if (nt >= (1ll << 31) - 64) return fail(CG_E_UNSUPPORTED, "grid too large");
@@ -675,10 +677,12 @@ cg_status cg_wcs_pix2world(const cg_wcs* wcs, int64_t n, const double* i, const 
                            double* lon_deg, double* lat_deg) {
   if (!wcs || n < 0 || (n > 0 && (!i || !j || !lon_deg || !lat_deg)))
     return fail(CG_E_INVALID, "bad arguments");
-  if (wcs->proj != CG_PROJ_CAR && wcs->proj != CG_PROJ_SIN)
+  if (wcs->proj != CG_PROJ_CAR && wcs->proj != CG_PROJ_SIN && wcs->proj != CG_PROJ_SFL &&
+      wcs->proj != CG_PROJ_ZEA)
     return fail(CG_E_UNSUPPORTED, "unknown projection");
-  if (wcs->proj == CG_PROJ_CAR && wcs->crval2 != 0.0)
-    return fail(CG_E_UNSUPPORTED, "oblique CAR (CRVAL2 != 0) is not supported");
+  if ((wcs->proj == CG_PROJ_CAR || wcs->proj == CG_PROJ_SFL) && wcs->crval2 != 0.0)
+    return fail(CG_E_UNSUPPORTED, "oblique %s (CRVAL2 != 0) is not supported",
+                wcs->proj == CG_PROJ_CAR ? "CAR" : "SFL");
   cg::WcsDev w;
   w.proj = wcs->proj;
   w.naxis1 = wcs->naxis1;

@@ -346,6 +346,29 @@ def config4(njobs: int = 64, scale: float = 1.0, device="cpu") -> list[Workload]
     return jobs
 
 
+def config_proj(proj: str, nchan: int = 2, device="cpu") -> Workload:
+    """Small maps in the two extra projections: ZEA over the north polar cap
+    (121x121 at 0.5 deg centred on the pole), SFL over the whole band
+    |lat| < 30 deg (361x61 at 1 deg centred on lon 180, so that the corners
+    fall outside the projection); area-uniform samples over a
+    slightly larger region, smooth field + point sources, Gaussian kernel of
+    one pixel sigma, support 3 sigma."""
+    g = rng(7 if proj == "ZEA" else 8)
+    if proj == "ZEA":
+        lon, lat = uniform_box(g, 60000, 0.0, 360.0, 55.0, 90.0)
+        wcs = wcs_sin(121, 121, 61.0, 61.0, 0.0, 90.0, -0.5, 0.5)
+        sigma = 0.5
+    else:
+        lon, lat = uniform_box(g, 80000, 0.0, 360.0, -35.0, 35.0)
+        wcs = wcs_car(361, 61, 181.0, 31.0, 180.0, -1.0, 1.0)
+        sigma = 1.0
+    wcs["proj"] = proj
+    data = allsky_field(g, lon, lat, nchan, 200, 3.0 * sigma, device=device)
+    return Workload(f"{proj} map {lon.shape[0]} x {wcs['naxis1']}x{wcs['naxis2']} x {nchan}ch",
+                    lon, lat, data, "f32", {"kind": "wcs", "wcs": wcs},
+                    ("gauss1d", (sigma,)), 3.0 * sigma, hpx_maxres=0.5 * sigma)
+
+
 def config_hpx(nside: int = 512, oversample: float = 15.0, nchan: int = 2,
                device="cpu") -> Workload:
     """HEALPix-map gridding of App. A.1: samples uniform on the sphere,

@@ -148,6 +148,26 @@ def test_sightlines_elliptical_fp32(nchan):
     compare_neighbours(counts, hashes, ref_ns)
 
 
+@pytest.mark.parametrize("proj", ["ZEA", "SFL"])
+def test_extra_projections(proj):
+    # the pixel centres of a ZEA map over the north pole and of an SFL band
+    # (pixels outside SFL's outline stay empty), FP32 and BF16 paths
+    wl = synth.config_proj(proj)
+    say(wl.name)
+    ref = oracle.grid_workload(wl)
+    g, R, W, (lon, lat, d) = _run_fp32(wl)
+    _check_values(R, W, ref)
+    counts, hashes = g.neighbour_stats(lon, lat)
+    ref_ns = oracle.neighbour_sets(wl.lon, wl.lat, *oracle.targets_of(wl), wl.support)
+    compare_neighbours(counts, hashes, ref_ns)
+    g.set_precision("bf16")
+    cube, w = g.grid_datacube(lon, lat, d)
+    g.sync()
+    ev = oracle.e_val(flat(cube, wl.nchan), ref["R"], ref["W"])
+    say(f"  bf16 e_val={ev:.2e}")
+    assert ev <= 1e-4
+
+
 # ------------------------------------------------------------ semantics
 
 def test_nside_independence():

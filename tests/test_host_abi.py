@@ -60,6 +60,9 @@ def test_host_argument_errors():
     with pytest.raises(cgp.CgError):
         cgp.wcs_pix2world({"NAXIS1": 4, "NAXIS2": 4, "CTYPE1": "RA---TAN", "CDELT1": 1, "CDELT2": 1},
                           [1.0], [1.0])
+    with pytest.raises(cgp.CgError):
+        cgp.wcs_pix2world({"NAXIS1": 4, "NAXIS2": 4, "CTYPE1": "RA---SFL", "CDELT1": 1, "CDELT2": 1,
+                           "CRVAL2": 10.0}, [1.0], [1.0])
 
 
 @pytest.mark.parametrize("hdr", [
@@ -74,6 +77,15 @@ def test_host_argument_errors():
     {"NAXIS": 2, "NAXIS1": 4320, "NAXIS2": 2160, "CTYPE1": "RA---CAR", "CTYPE2": "DEC--CAR",
      "CRPIX1": 2160.5, "CRPIX2": 1080.5, "CRVAL1": 0.0, "CRVAL2": 0.0,
      "CDELT1": -1 / 12, "CDELT2": 1 / 12},
+    {"NAXIS": 2, "NAXIS1": 400, "NAXIS2": 200, "CTYPE1": "RA---SFL", "CTYPE2": "DEC--SFL",
+     "CRPIX1": 200.5, "CRPIX2": 100.5, "CRVAL1": 30.0, "CRVAL2": 0.0,
+     "CDELT1": -1.0, "CDELT2": 1.0},
+    {"NAXIS": 2, "NAXIS1": 300, "NAXIS2": 300, "CTYPE1": "RA---ZEA", "CTYPE2": "DEC--ZEA",
+     "CRPIX1": 150.5, "CRPIX2": 150.5, "CRVAL1": 200.0, "CRVAL2": -35.0,
+     "CDELT1": -0.8, "CDELT2": 0.8},
+    {"NAXIS": 2, "NAXIS1": 120, "NAXIS2": 120, "CTYPE1": "GLON-ZEA", "CTYPE2": "GLAT-ZEA",
+     "CRPIX1": 60.5, "CRPIX2": 60.5, "CRVAL1": 0.0, "CRVAL2": 90.0,
+     "CDELT1": -0.05, "CDELT2": 0.05},
 ])
 def test_library_wcs_matches_oracle(hdr):
     g = np.random.default_rng(0)
