@@ -23,6 +23,12 @@ Kernels (readings where the paper is silent):
 * 'gauss1d', (sigma,): w = exp(-d^2 / (2 sigma^2))  (peak one; Listing 1
   uses 'gauss1d' with a sigma parameter; Eq. 3 makes the normalisation of
   w irrelevant for R).
+* 'tapered_sinc', (sigma, b): w = exp(-d^2 / (2 sigma^2)) sin(pi d/b) / (pi d/b),
+  the sin(ax)/ax kernel the paper names (Sect. 5, a = pi / b) under a
+  Gaussian taper (reading: a finite support needs one).
+* 'table', (dmax, w_0, ..., w_{n-1}): a radial profile of arbitrary shape
+  (the abstract: a kernel of arbitrary shape), w_k at d = k dmax / (n - 1),
+  linearly interpolated, zero beyond dmax.
 * 'gauss2d', (sigma_maj, sigma_min, pa): elliptical Gaussian in true world
   coordinates (Sect. 2.1, Fig. 1).  With beta the bearing of the sample
   seen from the target (north through east) and pa the position angle of
@@ -92,6 +98,18 @@ def kernel_weight(kernel, d, tlon, tlat, slon, slat):
         sb = np.sin(beta - p)
         q = cb * cb / (a * a) + sb * sb / (b * b)
         return np.exp(-0.5 * d * d * q)
+    if kind == "tapered_sinc":
+        # the sin(ax)/ax kernel of Sect. 5 with a = pi / b, under a Gaussian
+        # taper of width sigma so that a finite support suffices
+        sigma, b = params
+        s, bb = np.radians(sigma), np.radians(b)
+        return np.exp(-(d * d) / (2.0 * s * s)) * np.sinc(d / bb)
+    if kind == "table":
+        # a radial profile of arbitrary shape (the abstract): values w_k at
+        # d_k = k dmax / (n - 1), linear in between, zero beyond dmax
+        dmax = np.radians(params[0])
+        w = np.asarray(params[1:], dtype=np.float64)
+        return np.interp(d, np.linspace(0.0, dmax, w.size), w, right=0.0)
     raise ValueError(f"unknown kernel {kind!r}")
 
 

@@ -216,6 +216,37 @@ def test_sfl_closed_forms():
     assert np.isnan(lo[0]) and np.isnan(la[0])
 
 
+def _one_pair(kernel, d_deg, support):
+    # one sample d_deg north of the target, value 1: R = 1 and W = w(d)
+    out = og.grid_bruteforce(np.array([30.0]), np.array([10.0 + d_deg]), np.ones((1, 1)),
+                             np.array([30.0]), np.array([10.0]), kernel, support)
+    return out["W"][0]
+
+
+def test_tapered_sinc_values():
+    # sinc zeros at d = b, 2b; sin(pi/2)/(pi/2) = 2/pi at d = b/2; taper exp(-1/2) at d = sigma
+    k = ("tapered_sinc", (1e6, 0.3))
+    assert _one_pair(k, 0.0, 1.0) == pytest.approx(1.0, abs=1e-15)
+    assert abs(_one_pair(k, 0.3, 1.0)) < 1e-12 and abs(_one_pair(k, 0.6, 1.0)) < 1e-12
+    assert _one_pair(k, 0.15, 1.0) == pytest.approx(2 / math.pi, rel=1e-12)
+    assert _one_pair(("tapered_sinc", (0.2, 1e6)), 0.2, 1.0) == pytest.approx(math.exp(-0.5), rel=1e-9)
+
+
+def test_table_values():
+    # a two-entry table is the linear ramp 1 - d/dmax; zero beyond dmax
+    k = ("table", (0.5, 1.0, 0.0))
+    assert _one_pair(k, 0.125, 1.0) == pytest.approx(0.75, rel=1e-12)
+    assert _one_pair(k, 0.6, 1.0) == 0.0
+    # a finely tabulated Gaussian grids like the Gaussian itself (linear
+    # interpolation error <= h^2 max|w''| / 8 = h^2 / (8 sigma^2))
+    sigma, n = 0.1, 4001
+    dk = np.linspace(0.0, 0.5, n)
+    tab = ("table", tuple([0.5] + list(np.exp(-dk ** 2 / (2 * sigma ** 2)))))
+    for d in (0.0123, 0.0777, 0.1999, 0.31):
+        assert _one_pair(tab, d, 0.5) == pytest.approx(math.exp(-d * d / (2 * sigma * sigma)),
+                                                       abs=((0.5 / (n - 1)) / sigma) ** 2 / 8 + 1e-12)
+
+
 def test_sin_equatorial_row_and_column():
     w = _sin_hdr(0.0)
     k = np.arange(1, 40)
