@@ -83,9 +83,14 @@ typedef enum cg_layout {
 
 typedef enum cg_kernel_type {
   CG_GAUSS1D = 0,  /* params = {sigma}: w = exp(-d^2 / (2 sigma^2))            (Listing 1) */
-  CG_GAUSS2D = 1   /* params = {sigma_maj, sigma_min, pa}: elliptical Gaussian in world
+  CG_GAUSS2D = 1,  /* params = {sigma_maj, sigma_min, pa}: elliptical Gaussian in world
                       coordinates (Sect. 2.1, Fig. 1); pa = position angle of the major
                       axis, east of north, at the target */
+  CG_TAPERED_SINC = 2, /* params = {sigma, b}: w = exp(-d^2 / (2 sigma^2)) sin(pi d/b) / (pi d/b),
+                          the sin(ax)/ax kernel of Sect. 5 (a = pi/b) under a Gaussian taper */
+  CG_TABLE = 3     /* params = {dmax, w_0, ..., w_{n-1}} (n >= 2): radial profile of arbitrary
+                      shape (abstract), w_k at d = k dmax/(n-1), linear in between, 0 beyond
+                      dmax */
 } cg_kernel_type;
 
 /* FITS/WCS projections (Calabretta & Greisen 2002): CAR and SFL
@@ -145,8 +150,11 @@ cg_status cg_create_healpix(cg_gridder** out, int64_t nside, int32_t order, int6
 
 /* set_kernel(kernel_type, kernel_params, kernel_support, hpx_maxres)
  * (Listing 1, Sect. 3.5).  params: host double[nparams] (1 for GAUSS1D, 3
- * for GAUSS2D; sigmas in degrees, 0 < sigma_min <= sigma_maj, pa in
- * degrees).  support_deg: radius beyond which samples are ignored (0 <
+ * for GAUSS2D, 2 for TAPERED_SINC, 3 to 65537 for TABLE; sigmas, b and dmax
+ * in degrees and > 0, 0 < sigma_min <= sigma_maj, pa in degrees, table
+ * values finite; the table is copied into the handle, after the device has
+ * finished earlier work).  The batch API takes
+ * GAUSS1D and GAUSS2D gridders only.  support_deg: radius beyond which samples are ignored (0 <
  * support < 90).  hpx_maxres_deg: resolution of the internal HEALPix grid;
  * nside = smallest power of two with sqrt(pi/3)/nside <= hpx_maxres (a
  * speed knob only: the support test is exact), unless cg_set_nside fixed

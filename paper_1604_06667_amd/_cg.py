@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libcg.so")
 OK, E_INVALID, E_STATE, E_OOM, E_UNSUPPORTED, E_DEVICE, E_INPUT = 0, -1, -2, -3, -4, -5, -6
 F64, F32, F16, BF16 = 0, 1, 2, 3
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
-KERNEL = {"gauss1d": 0, "gauss2d": 1}
+KERNEL = {"gauss1d": 0, "gauss2d": 1, "tapered_sinc": 2, "table": 3}
 PROJ = {"CAR": 0, "SIN": 1, "SFL": 2, "ZEA": 3}
 LAYOUT = {"channel": 0, "target": 1}
 

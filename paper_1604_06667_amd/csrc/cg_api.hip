@@ -320,6 +320,34 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
     kp.kmin = kLog2e / (2.0 * b * b);
     kp.cospa = cos(pa);
     kp.sinpa = sin(pa);
+  } else if (kernel_type == CG_TAPERED_SINC) {
+    if (nparams != 2) return fail(CG_E_INVALID, "tapered sinc takes 2 parameters (sigma, b)");
+    const double s = params[0] * kDeg, b = params[1] * kDeg;
+    if (!(s > 0.0 && b > 0.0) || !isfinite(s) || !isfinite(b))
+      return fail(CG_E_INVALID, "sigma and b must be > 0");
+    kp.type = 2;
+    kp.k1 = kLog2e / (2.0 * s * s);
+    kp.ks = cg::hpx::kPi / b;
+  } else if (kernel_type == CG_TABLE) {
+    if (nparams < 3 || nparams > 65537)
+      return fail(CG_E_INVALID, "table takes dmax and 2 to 65536 values");
+    const double dmax = params[0] * kDeg;
+    if (!(dmax > 0.0) || !isfinite(dmax)) return fail(CG_E_INVALID, "dmax must be > 0");
+    for (int32_t k = 1; k < nparams; ++k)
+      if (!isfinite(params[k])) return fail(CG_E_INVALID, "table values must be finite");
+    {
+      const cg_status sd = set_dev(g);
+      if (sd != CG_OK) return sd;
+    }
+    // earlier grid calls may still read the previous table
+    CG_HIP(hipDeviceSynchronize(), "sync before the kernel table changes");
+    CG_HIP(ensure(g->ktab, sizeof(double) * (nparams - 1)), "alloc kernel table");
+    CG_HIP(hipMemcpy(g->ktab.p, params + 1, sizeof(double) * (nparams - 1), hipMemcpyHostToDevice),
+           "upload kernel table");
+    kp.type = 3;
+    kp.tab = g->ktab.as<double>();
+    kp.ntab = nparams - 1;
+    kp.tinv = (double)(nparams - 2) / dmax;
   } else {
     return fail(CG_E_INVALID, "unknown kernel type %d", kernel_type);
   }

@@ -208,6 +208,8 @@ cg_status upload_tables(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
     q.cube = in[j].cube_out;
     cube_strides(g, &q.cst, &q.tst);
     q.wout = in[j].weights_out;
+    if (g->kp.type > 1)
+      return fail(CG_E_UNSUPPORTED, "job %d: batches take gauss1d and gauss2d kernels", j);
     q.kp = g->kp;
     q.rho = g->support_rad + 1e-9;
   }
@@ -369,6 +371,8 @@ cg_status cg_batch_create(cg_batch** out, cg_gridder* const* jobs, int32_t njobs
     if (g->prec == CG_PREC_FP32)
       return fail(CG_E_UNSUPPORTED, "job %d: batches use the matrix-core precisions", j);
     if (g->prec != jobs[0]->prec) return fail(CG_E_UNSUPPORTED, "mixed precisions in one batch");
+    if (g->kp.type > 1)
+      return fail(CG_E_UNSUPPORTED, "job %d: batches take gauss1d and gauss2d kernels", j);
     if (g->device != jobs[0]->device) return fail(CG_E_UNSUPPORTED, "mixed devices in one batch");
     for (int k = 0; k < j; ++k)
       if (jobs[k] == g) return fail(CG_E_INVALID, "job %d repeats gridder of job %d", j, k);

@@ -100,6 +100,7 @@ struct cg_gridder {
   cgh::DevBuf flag;
   cgh::DevBuf zrow;   // nchan zeros of the widest data type
   cgh::DevBuf rec;   // per-sample record in input order (unit vector, narrow data)
+  cgh::DevBuf ktab;  // tabulated kernel profile (CG_TABLE)
   cgh::DevBuf keys, vals, keys2, vals2, hist, ring_off, sx, sdata, ranges, nranges, ncand, cand_off,
       cand, crow, cxyz;
   const uint32_t* sorted_keys = nullptr;

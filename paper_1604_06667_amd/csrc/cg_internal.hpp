@@ -18,11 +18,15 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 
 // Kernel constants derived on the host by set_kernel.
 struct KernelParams {
-  int type;          // 0 gauss1d, 1 gauss2d
+  int type;          // 0 gauss1d, 1 gauss2d, 2 tapered sinc, 3 tabulated radial profile
   double cs2;        // squared chord of the support radius: d <= r_s  <=>  c^2 <= cs2
-  double k1;         // gauss1d: log2(e) / (2 sigma^2)   (exponent in base 2, per rad^2)
+  double k1;         // gauss1d, tapered sinc: log2(e) / (2 sigma^2)   (base-2 exponent per rad^2)
   double kmaj, kmin; // gauss2d: log2(e) / (2 sigma_maj^2), log2(e) / (2 sigma_min^2)
   double cospa, sinpa;
+  double ks;         // tapered sinc: pi / b (per rad)
+  const double* tab; // tabulated profile: ntab values at d = k / tinv (device memory)
+  int ntab;
+  double tinv;       // (ntab - 1) / dmax (per rad)
 };
 
 // Device-side description of one tile's candidate list and target slots.
@@ -126,11 +130,29 @@ __device__ __forceinline__ float exp2_neg(double x) {
 // projection on the tangent plane at the target; with a, b the unit
 // vectors of the major and minor axis there, u = d.a, v = d.b and
 // cos^2(beta - pa) = u^2 / (u^2 + v^2).
+// Radial kernels of arbitrary shape at distance d (rad): the tapered sinc
+// exp(-d^2 / 2 sigma^2) sin(pi d / b) / (pi d / b), or the tabulated profile
+// interpolated linearly (zero beyond its last point).
+__device__ __forceinline__ double radial_weight(const KernelParams& kp, double d2) {
+  const double d = sqrt(d2);
+  if (kp.type == 2) {
+    const double a = kp.ks * d;
+    return (double)exp2_neg(d2 * kp.k1) * (a > 0.0 ? sin(a) / a : 1.0);
+  }
+  const double u = d * kp.tinv;
+  const int last = kp.ntab - 1;
+  if (!(u < (double)last)) return u == (double)last ? kp.tab[last] : 0.0;
+  const int i = (int)u;
+  const double f = u - (double)i;
+  return kp.tab[i] + f * (kp.tab[i + 1] - kp.tab[i]);
+}
+
 __device__ __forceinline__ float pair_weight(const KernelParams& kp, double c2, double dx, double dy,
                                              double dz, double ax, double ay, double az, double bx,
                                              double by, double bz) {
   const double d2 = chord2_to_d2(c2);
   if (kp.type == 0) return exp2_neg(d2 * kp.k1);
+  if (kp.type >= 2) return (float)radial_weight(kp, d2);
   const double u = dx * ax + dy * ay + dz * az;
   const double v = dx * bx + dy * by + dz * bz;
   const double uv = u * u + v * v;

@@ -56,9 +56,12 @@ static void launch_cfg(const TileView& tv, const KernelParams& kp, const void* d
   if (kp.type == 0) {
     if (full) CG_MFMA_LAUNCH(0, true);
     else CG_MFMA_LAUNCH(0, false);
-  } else {
+  } else if (kp.type == 1) {
     if (full) CG_MFMA_LAUNCH(1, true);
     else CG_MFMA_LAUNCH(1, false);
+  } else {
+    if (full) CG_MFMA_LAUNCH(3, true);
+    else CG_MFMA_LAUNCH(3, false);
   }
 #undef CG_MFMA_LAUNCH
 }

@@ -130,7 +130,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   __shared__ double s_red[2][NW][kTile];
   __shared__ double s_wfin[2][kTile];
   __shared__ double s_tg[kTile][3];                    // target unit vectors
-  __shared__ float s_ax[KT == 0 ? 1 : kTile][3];       // major axis at the target (elliptical)
+  __shared__ float s_ax[(KT == 1 || KT == 2) ? kTile : 1][3];   // major axis at the target (elliptical)
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t ns = tv.nslots;
@@ -139,7 +139,9 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   const int cl = lane & 31;      // channel within a 32-channel block / target within a 32-target block
   const int kh = lane >> 5;      // which 8 samples of the chunk this lane holds
   const int64_t cbase = c0 + wv * BPW * 32 + cl;   // this lane's channel in block 0
-  // KT 2: kernel type chosen at run time (batched jobs of both types)
+  // KT: 0 gauss1d, 1 gauss2d, 2 either, chosen at run time (batched jobs of
+  // both types), 3 a radial kernel of arbitrary shape (tapered sinc or
+  // tabulated profile, chosen at run time)
   const bool ell = KT == 1 || (KT == 2 && kp.type == 1);
   bool bvalid[BPW];    // this lane's channel of block b exists
   bool bany[BPW];      // block b has any channel (uniform over the wavefront)
@@ -155,7 +157,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     s_tg[t][0] = x;
     s_tg[t][1] = ldg<GL>(tv.txyz, ns + wslot);
     s_tg[t][2] = ldg<GL>(tv.txyz, 2 * ns + wslot);
-    if constexpr (KT != 0) {
+    if constexpr (KT == 1 || KT == 2) {
       // major axis: north turned towards east by the position angle
       double a[3] = {0.0, 0.0, 0.0};
       if (ell && isfinite(x)) {
@@ -229,6 +231,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   // the launch) take the two leading terms of d^2 = c^2 (1 + c^2/12 + ...)
   // and rq = 1 + c^2/3 + ..., whose next terms are below 1e-8 relative.
   const float k1f = (float)kp.k1, kminf = (float)kp.kmin, kdf = (float)(kp.kmaj - kp.kmin);
+  const float ksf = (float)kp.ks, tinvf = (float)kp.tinv;
   const bool short_support = kp.cs2 <= 1e-4;
   auto weight = [&](int rb, int wb, int k) {
     const double dx = s_c[rb][k][0] - s_tg[nw][0];
@@ -248,13 +251,37 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
       rq = uv > 0.0f ? d2 * __builtin_amdgcn_rcpf(uv) : 1.0f;
     }
     float x = d2 * k1f;
-    if constexpr (KT != 0) {
+    if constexpr (KT == 1 || KT == 2) {
       if (ell) {
         const float u = (float)dx * s_ax[nw][0] + (float)dy * s_ax[nw][1] + (float)dz * s_ax[nw][2];
         x = d2 * kminf + kdf * (u * u) * rq;
       }
     }
-    const float w = c2 <= kp.cs2 ? __builtin_amdgcn_exp2f(-x) : 0.0f;
+    float w;
+    if constexpr (KT == 3) {
+      // radial kernels of arbitrary shape: the tapered sinc, or the
+      // tabulated profile interpolated linearly (zero past its last point)
+      const float d = sqrtf(d2);
+      float v;
+      if (kp.type == 2) {
+        const float a = ksf * d;
+        v = __builtin_amdgcn_exp2f(-x) * (a > 0.0f ? sinf(a) / a : 1.0f);
+      } else {
+        const float u = d * tinvf;
+        const int last = kp.ntab - 1;
+        if (u < (float)last) {
+          const int i = (int)u;
+          const float f = u - (float)i;
+          const float t0 = (float)kp.tab[i], t1 = (float)kp.tab[i + 1];
+          v = t0 + f * (t1 - t0);
+        } else {
+          v = u == (float)last ? (float)kp.tab[last] : 0.0f;
+        }
+      }
+      w = c2 <= kp.cs2 ? v : 0.0f;
+    } else {
+      w = c2 <= kp.cs2 ? __builtin_amdgcn_exp2f(-x) : 0.0f;
+    }
     const uint16_t whi = to_bits<F16>(w);
     float wr = from_bits<F16>(whi);
     s_wt[wb][0][nw * KP + k] = whi;

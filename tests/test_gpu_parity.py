@@ -168,6 +168,50 @@ def test_extra_projections(proj):
     assert ev <= 1e-4
 
 
+def _radial_kernels():
+    dmax = 4.5 * ARC
+    d = np.linspace(0.0, dmax, 64)
+    prof = np.exp(-d ** 2 / (2 * (1.5 * ARC) ** 2)) * (1 - (d / dmax) ** 2)
+    return [("tapered_sinc", (2.0 * ARC, 1.5 * ARC)),
+            ("table", tuple([dmax] + list(prof))),
+            ("table", (3.0 * ARC, 1.0, 0.0))]
+
+
+@pytest.mark.parametrize("kidx", [0, 1, 2])
+@pytest.mark.parametrize("nchan", [3, 40])
+def test_radial_kernels_of_any_shape(kidx, nchan):
+    # the tapered sinc (negative lobes) and tabulated profiles, FP32 paths
+    # (narrow and wide) and, for the cube, the BF16 matrix-core path
+    wl = synth.config2(scale=0.05, nchan=nchan)
+    wl.kernel = _radial_kernels()[kidx]
+    say(f"{wl.name} kernel={wl.kernel[0]} n={len(wl.kernel[1])}")
+    ref = oracle.grid_workload(wl)
+    g, R, W, (lon, lat, d) = _run_fp32(wl)
+    m = np.abs(ref["W"]) > 1e-3 * np.abs(ref["W"]).max()   # the sinc's weights can cancel
+    ev = oracle.e_val(R[:, m], ref["R"][:, m], ref["W"][m])
+    ew = float(np.abs(W - ref["W"]).max() / np.abs(ref["W"]).max())
+    say(f"  fp32 e_val={ev:.2e} e_W={ew:.2e}")
+    assert ev <= TOL32 and ew <= TOL32
+    if nchan >= 32:
+        g.set_precision("bf16")
+        cube, w = g.grid_datacube(lon, lat, d)
+        g.sync()
+        Rb = flat(cube, wl.nchan)
+        ev = oracle.e_val(Rb[:, m], ref["R"][:, m], ref["W"][m])
+        say(f"  bf16 e_val={ev:.2e}")
+        assert ev <= 1e-4
+
+
+def test_radial_kernels_rejected_in_batches():
+    import paper_1604_06667_amd as cgp
+    torch = _torch()
+    wl = synth.config2(scale=0.03, nchan=64)
+    wl.kernel = _radial_kernels()[0]
+    g = make_gridder(wl, "bf16")
+    with pytest.raises(cgp.CgError):
+        cgp.Batch([g], torch.bfloat16)
+
+
 # ------------------------------------------------------------ semantics
 
 def test_nside_independence():
