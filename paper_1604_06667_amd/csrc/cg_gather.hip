@@ -52,7 +52,7 @@ __device__ __forceinline__ float qnan_f() { return __int_as_float(0x7fc00000); }
 // of other targets.  Sums per lane run in candidate order, as in the
 // definition.
 
-template <int CMAX>
+template <int CMAX, bool RADIAL>
 __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
                                                   const float* __restrict__ sdata, int64_t nchan,
                                                   OutView ov) {
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
       inside &= inside - 1;
       const double dx = s_x[k] - tx, dy = s_y[k] - ty, dz = s_z[k] - tz;
       const double c2 = dx * dx + dy * dy + dz * dz;
-      const float w = c2 <= kp.cs2 ? pair_weight(kp, c2, dx, dy, dz, ax[0], ax[1], ax[2], bx[0],
+      const float w = c2 <= kp.cs2 ? pair_weight<RADIAL>(kp, c2, dx, dy, dz, ax[0], ax[1], ax[2], bx[0],
                                                  bx[1], bx[2])
                                    : 0.0f;
       pw += w;
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
           if (KT == 0)
             w = exp2_neg(chord2_to_d2(c2) * kp.k1);
           else
-            w = pair_weight(kp, c2, dx, dy, dz, s_t[tt][3], s_t[tt][4], s_t[tt][5], s_t[tt][6],
+            w = pair_weight<KT == 3>(kp, c2, dx, dy, dz, s_t[tt][3], s_t[tt][4], s_t[tt][5], s_t[tt][6],
                             s_t[tt][7], s_t[tt][8]);
         }
       }
@@ -345,8 +345,11 @@ static void launch_cl(const TileView& tv, const KernelParams& kp, const void* da
   if (kp.type == 0)
     hipLaunchKernelGGL((k_gather_cl<VEC, 0, T>), g, b, 0, st, tv, kp, (const T*)data, ld, nchan,
                        vec_ok, ov);
-  else
+  else if (kp.type == 1)
     hipLaunchKernelGGL((k_gather_cl<VEC, 1, T>), g, b, 0, st, tv, kp, (const T*)data, ld, nchan,
+                       vec_ok, ov);
+  else
+    hipLaunchKernelGGL((k_gather_cl<VEC, 3, T>), g, b, 0, st, tv, kp, (const T*)data, ld, nchan,
                        vec_ok, ov);
 }
 
@@ -367,11 +370,19 @@ hipError_t launch_gather_fp32(const TileView& tv, const KernelParams& kp, const 
   if (tv.ntiles <= 0) return hipSuccess;
   if (nchan <= kSmallC) {
     const dim3 g((unsigned)tv.ntiles), b(64);
-    if (nchan <= 1) hipLaunchKernelGGL(k_gather_tl<1>, g, b, 0, st, tv, kp, sdata, nchan, ov);
-    else if (nchan <= 2) hipLaunchKernelGGL(k_gather_tl<2>, g, b, 0, st, tv, kp, sdata, nchan, ov);
-    else if (nchan <= 4) hipLaunchKernelGGL(k_gather_tl<4>, g, b, 0, st, tv, kp, sdata, nchan, ov);
-    else if (nchan <= 8) hipLaunchKernelGGL(k_gather_tl<8>, g, b, 0, st, tv, kp, sdata, nchan, ov);
-    else hipLaunchKernelGGL(k_gather_tl<16>, g, b, 0, st, tv, kp, sdata, nchan, ov);
+#define CG_TL(C)                                                                      \
+  do {                                                                                \
+    if (kp.type >= 2)                                                                 \
+      hipLaunchKernelGGL((k_gather_tl<C, true>), g, b, 0, st, tv, kp, sdata, nchan, ov);  \
+    else                                                                              \
+      hipLaunchKernelGGL((k_gather_tl<C, false>), g, b, 0, st, tv, kp, sdata, nchan, ov); \
+  } while (0)
+    if (nchan <= 1) CG_TL(1);
+    else if (nchan <= 2) CG_TL(2);
+    else if (nchan <= 4) CG_TL(4);
+    else if (nchan <= 8) CG_TL(8);
+    else CG_TL(16);
+#undef CG_TL
   } else if (nchan <= 64) {
     launch_cl_dt<1>(tv, kp, data, dtype, ld, nchan, ov, st);
   } else if (nchan <= 128) {

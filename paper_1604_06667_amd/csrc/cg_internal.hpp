@@ -147,12 +147,16 @@ __device__ __forceinline__ double radial_weight(const KernelParams& kp, double d
   return kp.tab[i] + f * (kp.tab[i + 1] - kp.tab[i]);
 }
 
+// RADIAL: the kernel is one of the radial shapes (types 2, 3); otherwise a
+// Gaussian (types 0, 1).  Separate instantiations keep the Gaussian loops
+// free of the radial code's registers.
+template <bool RADIAL>
 __device__ __forceinline__ float pair_weight(const KernelParams& kp, double c2, double dx, double dy,
                                              double dz, double ax, double ay, double az, double bx,
                                              double by, double bz) {
   const double d2 = chord2_to_d2(c2);
+  if constexpr (RADIAL) return (float)radial_weight(kp, d2);
   if (kp.type == 0) return exp2_neg(d2 * kp.k1);
-  if (kp.type >= 2) return (float)radial_weight(kp, d2);
   const double u = dx * ax + dy * ay + dz * az;
   const double v = dx * bx + dy * by + dz * bz;
   const double uv = u * u + v * v;
