@@ -346,6 +346,46 @@ def config4(njobs: int = 64, scale: float = 1.0, device="cpu") -> list[Workload]
     return jobs
 
 
+def config_stripes(spacing: float, psf_fwhm: float = 0.1, field: float = 1.5,
+                   nsrc: int = 3000, along: float = 0.05) -> Workload:
+    """Scan-line sampling of App. A.2: a quasi-continuous field of ``nsrc``
+    point sources (amplitudes U[0.1, 1]) seen through a Gaussian PSF of FWHM
+    ``psf_fwhm`` deg, sampled densely (every ``along`` x PSF) along horizontal
+    stripes ``spacing`` x PSF apart over a ``field`` x ``field`` deg map at
+    (180, 0) deg; no noise.  Target: the field as a CAR grid at 0.1 x PSF.
+    The same sources for every spacing; their list is in ``meta`` so that
+    the smoothed sky can be evaluated analytically.  The kernel set here is
+    a placeholder (the study varies it)."""
+    g = rng(9)
+    half = 0.5 * field
+    margin = 3.0 * psf_fwhm
+    src_lon = g.uniform(180.0 - half - margin, 180.0 + half + margin, nsrc)
+    src_lat = g.uniform(-half - margin, half + margin, nsrc)
+    src_amp = g.uniform(0.1, 1.0, nsrc)
+    d = spacing * psf_fwhm
+    lat_rows = np.arange(-half + 0.5 * d, half, d)
+    lon_cols = np.arange(180.0 - half, 180.0 + half + 1e-9, along * psf_fwhm)
+    lon = np.tile(lon_cols, lat_rows.size)
+    lat = np.repeat(lat_rows, lon_cols.size)
+    psf_sigma = psf_fwhm * FWHM_TO_SIGMA
+    v = np.zeros(lon.shape[0])
+    for k in range(nsrc):
+        dx = (lon - src_lon[k]) * math.cos(math.radians(src_lat[k]))
+        dy = lat - src_lat[k]
+        v += src_amp[k] * np.exp(-(dx * dx + dy * dy) / (2.0 * psf_sigma * psf_sigma))
+    pix = 0.1 * psf_fwhm
+    n = int(round(field / pix)) + 1
+    wcs = wcs_car(n, n, 0.5 * (n + 1), 0.5 * (n + 1), 180.0, -pix, pix)
+    sig = 0.5 * psf_fwhm * FWHM_TO_SIGMA
+    import torch
+    return Workload(f"App.A.2 stripes {spacing:.1f} PSF apart: {lon.shape[0]} samples x {n}x{n} CAR",
+                    lon, lat, torch.as_tensor(v[:, None].astype(np.float32)), "f32",
+                    {"kind": "wcs", "wcs": wcs},
+                    ("gauss1d", (sig,)), 5.0 * sig, hpx_maxres=0.5 * sig,
+                    meta={"src_lon": src_lon, "src_lat": src_lat, "src_amp": src_amp,
+                          "psf_sigma": psf_sigma, "psf_fwhm": psf_fwhm, "field": field})
+
+
 def config_proj(proj: str, nchan: int = 2, device="cpu") -> Workload:
     """Small maps in the two extra projections: ZEA over the north polar cap
     (121x121 at 0.5 deg centred on the pole), SFL over the whole band
