@@ -8,8 +8,12 @@ using namespace cgh;
 bool small_c(const cg_gridder* g) { return g->nchan <= cg::kSmallC && g->prec == CG_PREC_FP32; }
 
 // HEALPix index, sort, ring offsets, permute and candidate lists for n samples.
+// full_records: the matrix-core contraction follows, which reads each
+// candidate's unit vector and input index from per-tile copies; the FP32
+// gathers and the statistics read them from the sorted arrays.
 cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_t n,
-                     const void* data, int32_t dtype, int64_t ld, bool with_data, hipStream_t st) {
+                     const void* data, int32_t dtype, int64_t ld, bool with_data,
+                     bool full_records, hipStream_t st) {
   cg_status s = ensure_span(g, st);
   if (s != CG_OK) return s;
   const int64_t nside = g->nside;
@@ -55,13 +59,16 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
   g->last_n = n;
   const int64_t tc = total > 0 ? total : 1;
   CG_HIP(ensure(g->cand, sizeof(uint32_t) * tc), "alloc candidates");
-  CG_HIP(ensure(g->crow, sizeof(uint32_t) * tc), "alloc candidates");
-  CG_HIP(ensure(g->cxyz, sizeof(double) * 3 * tc), "alloc candidates");
-  g->ncap = tc;
+  if (full_records) {
+    CG_HIP(ensure(g->crow, sizeof(uint32_t) * tc), "alloc candidates");
+    CG_HIP(ensure(g->cxyz, sizeof(double) * 3 * tc), "alloc candidates");
+    g->ncap = tc;
+  }
   CG_HIP(cg::launch_expand(g->range_off.as<uint64_t>(), g->ranges.as<uint32_t>(),
                            g->nranges.as<uint32_t>(), g->cand_off.as<uint64_t>(), g->ntiles,
                            g->sorted_vals, g->sx.as<double>(), n, g->cand.as<uint32_t>(),
-                           g->crow.as<uint32_t>(), g->cxyz.as<double>(), g->ncap, st),
+                           g->crow.as<uint32_t>(), g->cxyz.as<double>(), g->ncap, full_records,
+                           st),
          "expand");
   return CG_OK;
 }
@@ -76,6 +83,10 @@ cg::TileView tile_view(const cg_gridder* g) {
   tv.cxyz = g->cxyz.as<double>();
   tv.nslots = g->nslots;
   tv.ncap = g->ncap;
+  // the sorted samples of the last lookup (unit vectors SoA, stride last_n)
+  tv.svals = g->sorted_vals;
+  tv.sx = g->sx.as<double>();
+  tv.nsorted = g->last_n;
   tv.ntiles = g->ntiles;
   tv.ntx = g->kind == 0 ? g->ntx : 0;
   return tv;
@@ -406,7 +417,8 @@ cg_status cg_grid(cg_gridder* g, const double* lon_deg, const double* lat_deg, c
   if ((s = set_dev(g)) != CG_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   CG_HIP(ensure(g->S, sizeof(float) * g->nchan * g->nslots), "alloc accumulators");
-  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g), st);
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g),
+                 g->prec != CG_PREC_FP32, st);
   if (s != CG_OK) return s;
   cg::OutView ov{};
   ov.S = g->S.as<float>();
@@ -434,7 +446,8 @@ cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* l
     if (weights_out) CG_HIP(cg::launch_fill(weights_out, g->ntarget, 0.0f, st), "fill");
     return CG_OK;
   }
-  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g), st);
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g),
+                 g->prec != CG_PREC_FP32, st);
   if (s != CG_OK) return s;
   cg::OutView ov{};
   ov.cube = cube_out;
@@ -521,7 +534,7 @@ cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double*
     return CG_OK;
   }
   if (!lon_deg || !lat_deg) return fail(CG_E_INVALID, "null coordinate pointer");
-  s = run_lookup(g, lon_deg, lat_deg, nsamples, nullptr, CG_F32, g->nchan, false, st);
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, nullptr, CG_F32, g->nchan, false, false, st);
   if (s != CG_OK) return s;
   CG_HIP(cg::launch_stats(tile_view(g), g->kp, g->slot_target.as<int32_t>(), counts, hashes, st),
          "stats");

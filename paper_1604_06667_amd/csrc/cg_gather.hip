@@ -70,15 +70,15 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
   double wacc = 0.0;
   const uint64_t c0 = tv.cand_off[tile], c1 = tv.cand_off[tile + 1];
-  const int64_t cap = tv.ncap;
+  const int64_t cap = tv.nsorted;
   const double thr = 1.0 - 0.5 * kp.cs2 - 2e-15;
   for (uint64_t base = c0; base < c1; base += kChunk) {
     const int kmax = (int)((c1 - base) < (uint64_t)kChunk ? (c1 - base) : (uint64_t)kChunk);
     if (lane < kmax) {
       const int64_t pos = tv.cand[base + lane];
-      s_x[lane] = tv.cxyz[base + lane];
-      s_y[lane] = tv.cxyz[cap + base + lane];
-      s_z[lane] = tv.cxyz[2 * cap + base + lane];
+      s_x[lane] = tv.sx[pos];
+      s_y[lane] = tv.sx[cap + pos];
+      s_z[lane] = tv.sx[2 * cap + pos];
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
         if (c < nchan) s_d[lane * CMAX + c] = sdata[pos * nchan + c];
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
   const int64_t c0 = pass * CB;
   const int t = threadIdx.x, lane = t & 63, wv_id = t >> 6;
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.ncap;
+  const int64_t cap = tv.nsorted;
   if (t < kTile) {
     const int64_t slot = tile * kTile + t;
     const double x = tv.txyz[slot];
@@ -229,10 +229,11 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
   for (uint64_t base = cb0; base < cb1; base += kChunk) {
     const int kmax = (int)((cb1 - base) < (uint64_t)kChunk ? (cb1 - base) : (uint64_t)kChunk);
     if (t < kmax) {
-      s_x[t] = tv.cxyz[base + t];
-      s_y[t] = tv.cxyz[cap + base + t];
-      s_z[t] = tv.cxyz[2 * cap + base + t];
-      s_row[t] = (int64_t)tv.crow[base + t] * ld;
+      const int64_t pos = tv.cand[base + t];
+      s_x[t] = tv.sx[pos];
+      s_y[t] = tv.sx[cap + pos];
+      s_z[t] = tv.sx[2 * cap + pos];
+      s_row[t] = (int64_t)tv.svals[pos] * ld;
     }
     __syncthreads();
     for (int r = wv_id; r < kmax; r += NWV) {
@@ -414,7 +415,7 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
   __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
   __shared__ uint32_t s_n[kChunk];
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.ncap;
+  const int64_t cap = tv.nsorted;
   const double tx = tv.txyz[slot], ty = tv.txyz[ns + slot], tz = tv.txyz[2 * ns + slot];
   int32_t cnt = 0;
   uint64_t h = 0;
@@ -422,10 +423,11 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
   for (uint64_t base = c0; base < c1; base += kChunk) {
     const int kmax = (int)((c1 - base) < (uint64_t)kChunk ? (c1 - base) : (uint64_t)kChunk);
     if (lane < kmax) {
-      s_x[lane] = tv.cxyz[base + lane];
-      s_y[lane] = tv.cxyz[cap + base + lane];
-      s_z[lane] = tv.cxyz[2 * cap + base + lane];
-      s_n[lane] = tv.crow[base + lane];
+      const int64_t pos = tv.cand[base + lane];
+      s_x[lane] = tv.sx[pos];
+      s_y[lane] = tv.sx[cap + pos];
+      s_z[lane] = tv.sx[2 * cap + pos];
+      s_n[lane] = tv.svals[pos];
     }
     __syncthreads();
     for (int k = 0; k < kmax; ++k) {

@@ -35,12 +35,16 @@ struct TileView {
   const double* tll;           // [2][nslots] target lon, lat in radians (gauss2d axes)
   const uint64_t* cand_off;    // [ntiles + 1] candidate offsets
   const uint32_t* cand;        // [ncand] sorted-sample position of each candidate
-  const uint32_t* crow;        // [ncand] input index (data row) of each candidate
-  const double* cxyz;          // [3][ncap] unit vector of each candidate
+  const uint32_t* crow;        // [ncand] input index (data row) of each candidate (matrix cores)
+  const double* cxyz;          // [3][ncap] unit vector of each candidate (matrix cores)
   int64_t nslots;
   int64_t ncap;                // stride of cxyz
   int64_t ntiles;
   int64_t ntx;                 // tiles per row of a WCS grid (0: sight lines)
+  // the sorted samples, read through cand by the FP32 gathers and statistics
+  const uint32_t* svals;       // [nsorted] input index
+  const double* sx;            // [3][nsorted] unit vector
+  int64_t nsorted;
 };
 
 // Block -> tile map that keeps consecutive tiles on one XCD: workgroups are
@@ -208,10 +212,11 @@ hipError_t launch_tile_ranges(int64_t ntiles, const int32_t* ring_first,
                               const uint64_t* range_off, const uint32_t* win,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st);
+// full: also the input index and unit vector of every candidate (crow, cxyz)
 hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
                          const uint64_t* cand_off, int64_t ntiles, const uint32_t* vals,
                          const double* sx, int64_t nsorted, uint32_t* cand, uint32_t* crow,
-                         double* cxyz, int64_t ncap, hipStream_t st);
+                         double* cxyz, int64_t ncap, bool full, hipStream_t st);
 
 // contraction kernels
 enum AccMode { ACC_OVERWRITE = 0, ACC_ADD = 1, ACC_FINAL = 2 };

@@ -483,13 +483,17 @@ hipError_t launch_tile_ranges(int64_t ntiles, const int32_t* ring_first,
 }
 
 // ---------------------------------------------------------------------------
-// Expand each tile's ranges into its list of candidates: sorted position,
-// input index and unit vector, so the contraction reads them in one level.
+// Expand each tile's ranges into its list of candidates: sorted position and
+// (FULL) input index and unit vector, so that the matrix-core contraction
+// reads its records in one level and contiguously.  The FP32 gathers read
+// the unit vector and input index from the sorted arrays at the position
+// instead, which saves writing and reading them again here.
 
 // One wavefront per tile.  Ranges are taken 64 at a time (one per lane); a
 // wavefront scan of their lengths places them, then every lane writes one
 // candidate per step, finding its range by binary search in LDS.  The data
 // row of a candidate is its value minus row0 (the job's first position).
+template <bool FULL>
 __device__ __forceinline__ void expand_body(const uint32_t* __restrict__ ranges, uint32_t nr,
                                             uint64_t out, const uint32_t* __restrict__ vals,
                                             int64_t row0, const double* __restrict__ sx,
@@ -526,16 +530,19 @@ __device__ __forceinline__ void expand_body(const uint32_t* __restrict__ ranges,
       const uint32_t pos = s_b[lo] + (p - s_start[lo]);
       const uint64_t o = out + p;
       cand[o] = pos;
-      crow[o] = (uint32_t)((int64_t)vals[pos] - row0);
-      cxyz[o] = sx[pos];
-      cxyz[ncap + o] = sx[nsorted + pos];
-      cxyz[2 * ncap + o] = sx[2 * nsorted + pos];
+      if constexpr (FULL) {
+        crow[o] = (uint32_t)((int64_t)vals[pos] - row0);
+        cxyz[o] = sx[pos];
+        cxyz[ncap + o] = sx[nsorted + pos];
+        cxyz[2 * ncap + o] = sx[2 * nsorted + pos];
+      }
     }
     out += tot;
     __syncthreads();
   }
 }
 
+template <bool FULL>
 __global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ range_off,
                                                const uint32_t* __restrict__ ranges,
                                                const uint32_t* __restrict__ nranges,
@@ -546,8 +553,8 @@ __global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ rang
                                                uint32_t* __restrict__ crow,
                                                double* __restrict__ cxyz, int64_t ncap) {
   const int64_t tile = blockIdx.x;
-  expand_body(ranges + 2 * range_off[tile], nranges[tile], cand_off[tile], vals, 0, sx, nsorted,
-              cand, crow, cxyz, ncap);
+  expand_body<FULL>(ranges + 2 * range_off[tile], nranges[tile], cand_off[tile], vals, 0, sx,
+                    nsorted, cand, crow, cxyz, ncap);
 }
 
 __global__ void __launch_bounds__(64) k_batch_expand(
@@ -561,8 +568,8 @@ __global__ void __launch_bounds__(64) k_batch_expand(
   const int64_t g = blockIdx.x;
   const int j = job_of(toff, njobs, g);
   const BatchJob& jb = jobs[j];
-  expand_body(ranges + 2 * (jb.rbase + jb.range_off[g - jb.toff]), nranges[g], cand_off[g], vals,
-              jb.noff, sx, nsorted, cand, crow, cxyz, ncap);
+  expand_body<true>(ranges + 2 * (jb.rbase + jb.range_off[g - jb.toff]), nranges[g], cand_off[g],
+                    vals, jb.noff, sx, nsorted, cand, crow, cxyz, ncap);
 }
 
 // ovf[0]: this pass overflows the candidate buffers (cleared every pass);
@@ -595,10 +602,14 @@ hipError_t launch_batch_expand(const BatchJob* jobs, const int64_t* toff, int nj
 hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
                          const uint64_t* cand_off, int64_t ntiles, const uint32_t* vals,
                          const double* sx, int64_t nsorted, uint32_t* cand, uint32_t* crow,
-                         double* cxyz, int64_t ncap, hipStream_t st) {
+                         double* cxyz, int64_t ncap, bool full, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_expand, dim3((unsigned)ntiles), dim3(64), 0, st, range_off, ranges, nranges,
-                     cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap);
+  if (full)
+    hipLaunchKernelGGL(k_expand<true>, dim3((unsigned)ntiles), dim3(64), 0, st, range_off, ranges,
+                       nranges, cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap);
+  else
+    hipLaunchKernelGGL(k_expand<false>, dim3((unsigned)ntiles), dim3(64), 0, st, range_off, ranges,
+                       nranges, cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap);
   return hipGetLastError();
 }
 
