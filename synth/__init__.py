@@ -409,6 +409,19 @@ def config_proj(proj: str, nchan: int = 2, device="cpu") -> Workload:
                     ("gauss1d", (sigma,)), 3.0 * sigma, hpx_maxres=0.5 * sigma)
 
 
+def config_hpx_tiny(nside: int, order: str = "ring", nsamples: int = 5000) -> Workload:
+    """A HEALPix map of 12 nside^2 pixels (nside 1, 2, 4: tiles straddling
+    base faces) from area-uniform samples with a smooth channel and a noise
+    channel (FP64); Gaussian kernel sigma 10 deg, support 25 deg."""
+    g = rng(100 + nside)
+    lon, lat = uniform_sphere(g, nsamples)
+    data = np.stack([np.cos(np.radians(lat)) * np.sin(np.radians(lon)),
+                     g.normal(0.0, 1.0, nsamples)], axis=1)
+    return Workload(f"tiny HEALPix map nside {nside} ({order})", lon, lat, data, "f64",
+                    {"kind": "healpix", "nside": int(nside), "order": order},
+                    ("gauss1d", (10.0,)), 25.0, hpx_maxres=5.0)
+
+
 def config_hpx(nside: int = 512, oversample: float = 15.0, nchan: int = 2,
                device="cpu") -> Workload:
     """HEALPix-map gridding of App. A.1: samples uniform on the sphere,

@@ -96,3 +96,17 @@ def test_hpx_map_rejects_bad_nside():
             cgp.HpxGrid(ns)
     with pytest.raises(ValueError):
         cgp.HpxGrid(4, "zorder")
+
+
+@pytest.mark.parametrize("nside,order", [(1, "ring"), (2, "nested"), (4, "ring")])
+def test_hpx_tiny_maps(nside, order):
+    # maps of 12, 48 and 192 pixels: one or a few tiles that straddle base
+    # faces, with padded slots
+    wl = synth.config_hpx_tiny(nside, order)
+    say(wl.name)
+    ref = oracle.grid_workload(wl)
+    g, R, W, (lo, la, d) = _run(wl, "fp32", oneshot=False)
+    ev = oracle.e_val(R, ref["R"], ref["W"])
+    ew = oracle.e_weights(W, ref["W"])
+    say(f"  e_val={ev:.3e} e_W={ew:.3e}")
+    assert R.shape == (2, 12 * nside * nside) and ev <= TOL32 and ew <= TOL32
