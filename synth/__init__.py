@@ -409,6 +409,19 @@ def config_proj(proj: str, nchan: int = 2, device="cpu") -> Workload:
                     ("gauss1d", (sigma,)), 3.0 * sigma, hpx_maxres=0.5 * sigma)
 
 
+def config_tiny_grid(nx: int, ny: int, nsamples: int = 3000) -> Workload:
+    """A SIN grid of nx x ny pixels at 1' (1x1 up to ragged sizes) at
+    (40, -20) deg with uniform samples over the grid plus a 5' margin, two
+    FP64 channels of unit Gaussian noise; kernel sigma 1.5', support 4.5'."""
+    g = rng(200 + nx)
+    wcs = wcs_sin(nx, ny, 0.5 * (nx + 1), 0.5 * (ny + 1), 40.0, -20.0, -ARCMIN, ARCMIN)
+    lon = 40.0 + g.uniform(-0.5, 0.5, nsamples) * (nx + 10) * ARCMIN
+    lat = -20.0 + g.uniform(-0.5, 0.5, nsamples) * (ny + 10) * ARCMIN
+    data = g.normal(size=(nsamples, 2))
+    return Workload(f"tiny {nx}x{ny} SIN grid", lon, lat, data, "f64", {"kind": "wcs", "wcs": wcs},
+                    ("gauss1d", (1.5 * ARCMIN,)), 4.5 * ARCMIN, hpx_maxres=0.75 * ARCMIN)
+
+
 def config_hpx_tiny(nside: int, order: str = "ring", nsamples: int = 5000) -> Workload:
     """A HEALPix map of 12 nside^2 pixels (nside 1, 2, 4: tiles straddling
     base faces) from area-uniform samples with a smooth channel and a noise

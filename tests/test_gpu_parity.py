@@ -296,13 +296,7 @@ def test_empty_and_invalid_inputs():
 def test_tiny_and_ragged_grids():
     torch = _torch()
     for nx, ny in ((1, 1), (9, 3), (17, 65)):
-        wcs = synth.wcs_sin(nx, ny, 0.5 * (nx + 1), 0.5 * (ny + 1), 40.0, -20.0, -ARC, ARC)
-        g0 = np.random.default_rng(nx)
-        lon = 40.0 + g0.uniform(-0.5, 0.5, 3000) * (nx + 10) * ARC
-        lat = -20.0 + g0.uniform(-0.5, 0.5, 3000) * (ny + 10) * ARC
-        data = g0.normal(size=(3000, 2))
-        wl = synth.Workload("tiny", lon, lat, data, "f64", {"kind": "wcs", "wcs": wcs},
-                            ("gauss1d", (1.5 * ARC,)), 4.5 * ARC, hpx_maxres=0.75 * ARC)
+        wl = synth.config_tiny_grid(nx, ny)
         say(f"grid {nx}x{ny}")
         ref = oracle.grid_workload(wl, method="brute")
         _, R, W, _ = _run_fp32(wl)
