@@ -182,6 +182,10 @@ def device_inputs(wl, dev):
     return lon, lat, data.contiguous()
 
 
+LOOKUP = "tiles"      # --lookup: 'tiles' or the sample-centric 'disk' lookup
+_GRIDDERS = []
+
+
 def make_gridder(wl, dev):
     import torch
     import paper_1604_06667_amd as cgp
@@ -198,6 +202,8 @@ def make_gridder(wl, dev):
         g.set_nside(wl.nside)
     res = wl.hpx_maxres or (0.5 * (params[0] if kind == "gauss1d" else params[1]))
     g.set_kernel(kind, params, wl.support, res)
+    g.set_lookup(LOOKUP)
+    _GRIDDERS.append(g)
     return g
 
 
@@ -209,6 +215,8 @@ def count_contributions(g, lon, lat, nchan):
 
 
 def base_line(a, wl_desc, value, ms, dtype, config, roof, cpu):
+    if LOOKUP != "tiles":
+        config = dict(config, lookup=LOOKUP)
     return {"metric": METRIC, "value": value, "unit": "contributions/s",
             "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -505,6 +513,9 @@ def main():
                     choices=["cube", "allsky", "batched", "sightlines", "healpix"])
     ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "bf16", "fp16"],
                     help="contraction of the cube workload")
+    ap.add_argument("--lookup", default="tiles", choices=["tiles", "disk"],
+                    help="candidate lookup: per tile of targets, or the sample-centric "
+                         "query disks shifted along rings (Sect. 3.3)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--cpu-block", type=int, default=384)
@@ -528,10 +539,19 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 3}))
         return
 
+    global LOOKUP
+    LOOKUP = a.lookup
+    if a.lookup != "tiles" and a.workload == "batched":
+        print("batches always use the tile lookup", file=sys.stderr)
+        sys.exit(2)
     dev = "cuda:0"
     run = {"cube": run_cube, "allsky": run_allsky, "batched": run_batched,
            "sightlines": run_sightlines, "healpix": run_healpix}[a.workload]
-    print(json.dumps(run(a, dev)), flush=True)
+    out = run(a, dev)
+    if LOOKUP == "disk" and _GRIDDERS:
+        npix, npairs = _GRIDDERS[-1].disk_stats()
+        out["disk_lookup"] = {"sample_pixels": npix, "tile_pixel_pairs": npairs}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -93,6 +93,19 @@ typedef enum cg_kernel_type {
                       dmax */
 } cg_kernel_type;
 
+/* How a grid call finds the samples near each target (cg_set_lookup).  Both
+ * give the same result: the lookup only proposes candidates, and the
+ * contraction keeps exactly the samples within the support. */
+typedef enum cg_lookup {
+  CG_LOOKUP_TILES = 0,  /* per tile of targets: the RING pixel windows of the union of the
+                           targets' support disks, turned into runs of sorted samples */
+  CG_LOOKUP_DISK = 1    /* sample-centric (Sect. 2.2 step 3, Sect. 3.3-3.4): one query disk
+                           per HEALPix ring around the pixel nearest longitude 180 deg, moved to
+                           every sample pixel by the integer shifts of Eq. 4-5, matched against
+                           targets hashed by their nearest pixel, then inverted into per-tile
+                           sample lists */
+} cg_lookup;
+
 /* FITS/WCS projections (Calabretta & Greisen 2002): CAR and SFL
  * (Sanson-Flamsteed, Listing 1) non-oblique; SIN and ZEA (zenithal
  * equal-area, Fig. 1) zenithal with LONPOLE = 180 deg. */
@@ -166,6 +179,23 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
 /* Fix the internal HEALPix nside (power of two, 1 <= nside <= 8192) instead of
  * deriving it from hpx_maxres.  Errors: CG_E_INVALID. */
 cg_status cg_set_nside(cg_gridder* g, int64_t nside);
+
+/* Select the lookup (cg_lookup) of this handle's grid, grid_datacube and
+ * neighbour_stats calls.  Default CG_LOOKUP_TILES.  CG_LOOKUP_DISK widens
+ * each query disk by the largest pixel radius of the sample's ring and of
+ * the target's ring, plus one pixel for the rounding of Eq. 4, so that it
+ * still finds every sample within the support; it waits for the device
+ * three times per call (to size its pair lists) and needs
+ * 4 nside (2 reach + 1) table entries, reach ~ 1.5 (support + 2 pixel radii)
+ * nside.  Batches always use the tile lookup.  Errors: CG_E_INVALID;
+ * grid calls in disk mode also CG_E_UNSUPPORTED (table above 2^28 entries
+ * or 2^32 - 1 pairs). */
+cg_status cg_set_lookup(cg_gridder* g, int32_t lookup);
+
+/* Statistics of the last grid call in CG_LOOKUP_DISK mode: distinct sample
+ * pixels and (tile, sample pixel) pairs before the inversion.  Errors:
+ * CG_E_INVALID. */
+cg_status cg_disk_stats(const cg_gridder* g, int64_t* pixels, int64_t* pairs);
 
 /* Select the contraction arithmetic (cg_prec).  Default CG_PREC_FP32.
  * Errors: CG_E_INVALID. */
@@ -356,6 +386,13 @@ cg_status cg_hpx_cap_ranges(int64_t nside, double lon_deg, double lat_deg, doubl
 cg_status cg_hpx_targets_ranges(int64_t nside, int64_t n, const double* lon_deg,
                                 const double* lat_deg, double rho_deg, int64_t* ranges,
                                 int64_t max_ranges, int64_t* nranges);
+/* The shifted query disk of CG_LOOKUP_DISK for one sample pixel (host):
+ * the RING pixel ranges of targets the lookup matches with RING pixel pix
+ * for support_deg, as inclusive pairs in ranges[2*k], ranges[2*k+1] (at
+ * most max_ranges pairs); *nranges receives the count.  Errors:
+ * CG_E_INVALID (bad arguments, or max_ranges too small). */
+cg_status cg_hpx_query_disk(int64_t nside, int64_t pix, double support_deg, int64_t* ranges,
+                            int64_t max_ranges, int64_t* nranges);
 /* WCS pixel centres (host): world coordinates of 1-based pixels (i, j);
  * NaN where the pixel has none. */
 cg_status cg_wcs_pix2world(const cg_wcs* wcs, int64_t n, const double* i, const double* j,

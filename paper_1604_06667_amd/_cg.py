@@ -17,6 +17,7 @@ OK, E_INVALID, E_STATE, E_OOM, E_UNSUPPORTED, E_DEVICE, E_INPUT = 0, -1, -2, -3,
 F64, F32, F16, BF16 = 0, 1, 2, 3
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 KERNEL = {"gauss1d": 0, "gauss2d": 1, "tapered_sinc": 2, "table": 3}
+LOOKUP = {"tiles": 0, "disk": 1}
 PROJ = {"CAR": 0, "SIN": 1, "SFL": 2, "ZEA": 3}
 LAYOUT = {"channel": 0, "target": 1}
 
@@ -52,6 +53,8 @@ SIGNATURES = {
     "cg_set_kernel": (_i32, [_vp, _i32, _P(_d), _i32, _d, _d]),
     "cg_set_nside": (_i32, [_vp, _i64]),
     "cg_set_precision": (_i32, [_vp, _i32]),
+    "cg_set_lookup": (_i32, [_vp, _i32]),
+    "cg_disk_stats": (_i32, [_vp, _P(_i64), _P(_i64)]),
     "cg_set_output_layout": (_i32, [_vp, _i32]),
     "cg_grid": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp]),
     "cg_get_datacube": (_i32, [_vp, _vp, _vp]),
@@ -81,6 +84,7 @@ SIGNATURES = {
     "cg_hpx_pix2ring": (_i32, [_i64, _i64, _vp, _vp, _vp]),
     "cg_hpx_ring_info": (_i32, [_i64, _i64, _P(_i64), _P(_i64), _P(_d)]),
     "cg_hpx_cap_ranges": (_i32, [_i64, _d, _d, _d, _vp, _i64, _P(_i64)]),
+    "cg_hpx_query_disk": (_i32, [_i64, _i64, _d, _vp, _i64, _P(_i64)]),
     "cg_hpx_targets_ranges": (_i32, [_i64, _i64, _vp, _vp, _d, _vp, _i64, _P(_i64)]),
     "cg_wcs_pix2world": (_i32, [_P(CgWcs), _i64, _vp, _vp, _vp, _vp]),
 }
@@ -209,6 +213,20 @@ class _Gridder:
 
     def set_nside(self, nside):
         check(lib().cg_set_nside(self._handle(), int(nside)))
+
+    def set_lookup(self, lookup):
+        """'tiles' (default) or 'disk': the sample-centric lookup of Sect. 3.3
+        (query disks shifted along rings, Eq. 4-5, then inverted)."""
+        if lookup not in LOOKUP:
+            raise CgError(E_INVALID, f"unknown lookup {lookup!r}")
+        check(lib().cg_set_lookup(self._handle(), LOOKUP[lookup]))
+
+    def disk_stats(self):
+        """(distinct sample pixels, (tile, pixel) pairs) of the last grid call
+        with the 'disk' lookup."""
+        a, b = C.c_int64(), C.c_int64()
+        check(lib().cg_disk_stats(self._handle(), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def set_precision(self, prec):
         if prec not in PREC:
@@ -523,6 +541,17 @@ def hpx_cap_ranges(nside, lon_deg, lat_deg, rho_deg, max_ranges=1 << 16):
     n = C.c_int64()
     check(lib().cg_hpx_cap_ranges(int(nside), float(lon_deg), float(lat_deg), float(rho_deg),
                                   _np_ptr(buf), int(max_ranges), C.byref(n)))
+    return buf[: 2 * n.value].reshape(-1, 2)
+
+
+def hpx_query_disk(nside, pix, support_deg, max_ranges=1 << 16):
+    """RING pixel ranges [lo, hi] of the shifted query disk that the 'disk'
+    lookup uses for sample pixel ``pix``."""
+    import numpy as np
+    buf = np.empty(2 * max_ranges, dtype=np.int64)
+    n = C.c_int64()
+    check(lib().cg_hpx_query_disk(int(nside), int(pix), float(support_deg), _np_ptr(buf),
+                                  int(max_ranges), C.byref(n)))
     return buf[: 2 * n.value].reshape(-1, 2)
 
 

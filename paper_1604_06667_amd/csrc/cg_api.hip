@@ -11,6 +11,123 @@ bool small_c(const cg_gridder* g) { return g->nchan <= cg::kSmallC && g->prec ==
 // full_records: the matrix-core contraction follows, which reads each
 // candidate's unit vector and input index from per-tile copies; the FP32
 // gathers and the statistics read them from the sorted arrays.
+// Set-up of the sample-centric lookup: targets sorted by their nearest
+// RING pixel with per-ring offsets (the hash table of Sect. 2.2), and the
+// reference query disk of every ring (Sect. 3.3).  Depends only on the
+// targets, the support and nside.
+cg_status ensure_disk(cg_gridder* g, hipStream_t st) {
+  if (g->disk_valid) return CG_OK;
+  const int64_t nside = g->nside, nsl = g->nslots;
+  const int64_t reach = cg::hpx::disk_ring_reach(nside, g->support_rad);
+  const int64_t entries = 4 * nside * (2 * reach + 1);
+  if (entries > (int64_t(1) << 28))
+    return fail(CG_E_UNSUPPORTED, "query-disk table of %lld entries (support too wide for nside)",
+                (long long)entries);
+  CG_HIP(ensure(g->dk_tkeys, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_tvals, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_tkeys2, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_tvals2, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_thist, sizeof(uint32_t) * cg::radix_hist_elems(nsl)), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_troff, sizeof(uint32_t) * (4 * nside + 1)), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_tab, sizeof(int2) * entries), "alloc disk lookup");
+  CG_HIP(cg::launch_target_keys(g->txyz.as<double>(), nsl, nside, g->dk_tkeys.as<uint32_t>(),
+                                g->dk_tvals.as<uint32_t>(), st),
+         "target keys");
+  bool in_tmp = false;
+  CG_HIP(cg::radix_sort(g->dk_tkeys.as<uint32_t>(), g->dk_tvals.as<uint32_t>(),
+                        g->dk_tkeys2.as<uint32_t>(), g->dk_tvals2.as<uint32_t>(),
+                        g->dk_thist.as<uint32_t>(), nsl, bits_for((uint64_t)cg::hpx::npix(nside)),
+                        &in_tmp, st),
+         "sort targets");
+  g->dk_tk = in_tmp ? g->dk_tkeys2.as<uint32_t>() : g->dk_tkeys.as<uint32_t>();
+  g->dk_ts = in_tmp ? g->dk_tvals2.as<uint32_t>() : g->dk_tvals.as<uint32_t>();
+  CG_HIP(cg::launch_ring_offsets(g->dk_tk, nsl, nside, g->dk_troff.as<uint32_t>(), st),
+         "target ring offsets");
+  CG_HIP(cg::launch_ref_disks(nside, reach, g->support_rad, g->dk_tab.as<int2>(), st),
+         "reference disks");
+  g->disk_reach = reach;
+  g->disk_valid = true;
+  return CG_OK;
+}
+
+// Sample-centric candidate ranges of a grid call (after the samples are
+// sorted): distinct sample pixels, their shifted query disks matched with
+// the targets as (tile, pixel) pairs, the pairs sorted by tile, and per tile
+// the merged ranges of sorted samples with their candidate counts.
+cg_status run_disk_lookup(cg_gridder* g, int64_t n, hipStream_t st) {
+  cg_status s = ensure_disk(g, st);
+  if (s != CG_OK) return s;
+  const int64_t nside = g->nside;
+  const uint32_t* nvalid = g->ring_off.as<uint32_t>() + 4 * nside;
+  CG_HIP(ensure(g->dk_flag, sizeof(uint64_t) * n), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_uoff, sizeof(uint64_t) * (n + 1)), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_upix, sizeof(uint32_t) * n), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_ustart, sizeof(uint32_t) * (n + 1)), "alloc disk lookup");
+  CG_HIP(cg::launch_run_flags(g->sorted_keys, nvalid, n, g->dk_flag.as<uint64_t>(), st),
+         "pixel runs");
+  CG_HIP(ensure(g->dk_scan, sizeof(uint64_t) * cg::scan_u64_wide_scratch(n)), "alloc disk lookup");
+  CG_HIP(cg::scan_u64_wide(g->dk_flag.as<uint64_t>(), g->dk_uoff.as<uint64_t>(), n,
+                           g->dk_scan.as<uint64_t>(), st),
+         "scan runs");
+  CG_HIP(cg::launch_run_compact(g->sorted_keys, nvalid, n, g->dk_uoff.as<uint64_t>(),
+                                g->dk_upix.as<uint32_t>(), g->dk_ustart.as<uint32_t>(), st),
+         "pixel runs");
+  CG_HIP(hipMemcpyAsync(g->h_word, g->dk_uoff.as<uint64_t>() + n, sizeof(uint64_t),
+                        hipMemcpyDeviceToHost, st),
+         "read runs");
+  CG_HIP(hipStreamSynchronize(st), "sync runs");
+  const int64_t nu = (int64_t)g->h_word[0];
+  CG_HIP(ensure(g->dk_cnt, sizeof(uint64_t) * nu), "alloc disk lookup");
+  CG_HIP(ensure(g->dk_off, sizeof(uint64_t) * (nu + 1)), "alloc disk lookup");
+  CG_HIP(cg::launch_disk_pairs(true, g->dk_upix.as<uint32_t>(), nu, nside, g->disk_reach,
+                               g->dk_tab.as<int2>(), g->dk_tk, g->dk_ts,
+                               g->dk_troff.as<uint32_t>(), nullptr, g->dk_cnt.as<uint64_t>(),
+                               nullptr, nullptr, st),
+         "count pairs");
+  CG_HIP(cg::scan_u64_wide(g->dk_cnt.as<uint64_t>(), g->dk_off.as<uint64_t>(), nu,
+                           g->dk_scan.as<uint64_t>(), st),
+         "scan pairs");
+  CG_HIP(hipMemcpyAsync(g->h_word, g->dk_off.as<uint64_t>() + nu, sizeof(uint64_t),
+                        hipMemcpyDeviceToHost, st),
+         "read pairs");
+  CG_HIP(hipStreamSynchronize(st), "sync pairs");
+  const int64_t np = (int64_t)g->h_word[0];
+  if (np >= 0xFFFFFFFFll)
+    return fail(CG_E_UNSUPPORTED, "%lld (tile, pixel) pairs (split the samples)", (long long)np);
+  g->last_upix = nu;
+  g->last_pairs = np;
+  const int64_t nt = g->ntiles;
+  CG_HIP(ensure(g->dk_pk, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->dk_pv, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->dk_pk2, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->dk_pv2, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->dk_phist, sizeof(uint32_t) * cg::radix_hist_elems(np)), "alloc pairs");
+  CG_HIP(ensure(g->dk_flag, sizeof(uint64_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->dk_rsx, sizeof(uint64_t) * (np + 1)), "alloc pairs");
+  CG_HIP(ensure(g->dk_scan, sizeof(uint64_t) * cg::scan_u64_wide_scratch(np)), "alloc pairs");
+  CG_HIP(ensure(g->dk_ranges, sizeof(uint32_t) * 2 * np), "alloc pairs");
+  CG_HIP(ensure(g->dk_range_off, sizeof(uint64_t) * (nt + 1)), "alloc pairs");
+  CG_HIP(cg::launch_disk_pairs(false, g->dk_upix.as<uint32_t>(), nu, nside, g->disk_reach,
+                               g->dk_tab.as<int2>(), g->dk_tk, g->dk_ts,
+                               g->dk_troff.as<uint32_t>(), g->dk_off.as<uint64_t>(), nullptr,
+                               g->dk_pk.as<uint32_t>(), g->dk_pv.as<uint32_t>(), st),
+         "write pairs");
+  bool in_tmp = false;
+  CG_HIP(cg::radix_sort(g->dk_pk.as<uint32_t>(), g->dk_pv.as<uint32_t>(), g->dk_pk2.as<uint32_t>(),
+                        g->dk_pv2.as<uint32_t>(), g->dk_phist.as<uint32_t>(), np,
+                        bits_for((uint64_t)nt), &in_tmp, st),
+         "sort pairs");
+  const uint32_t* pk = in_tmp ? g->dk_pk2.as<uint32_t>() : g->dk_pk.as<uint32_t>();
+  const uint32_t* pv = in_tmp ? g->dk_pv2.as<uint32_t>() : g->dk_pv.as<uint32_t>();
+  CG_HIP(cg::launch_disk_ranges(pk, pv, np, g->dk_ustart.as<uint32_t>(), g->dk_flag.as<uint64_t>(),
+                                g->dk_rsx.as<uint64_t>(), g->dk_scan.as<uint64_t>(), nt,
+                                g->dk_ranges.as<uint32_t>(),
+                                g->dk_range_off.as<uint64_t>(), g->nranges.as<uint32_t>(),
+                                g->ncand.as<uint64_t>(), st),
+         "disk ranges");
+  return CG_OK;
+}
+
 cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_t n,
                      const void* data, int32_t dtype, int64_t ld, bool with_data,
                      bool full_records, hipStream_t st) {
@@ -43,11 +160,20 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
                             ld, g->nchan, with_data, npack, n, g->sx.as<double>(),
                             g->sdata.as<float>(), st),
          "permute");
-  CG_HIP(cg::launch_tile_ranges(g->ntiles, g->ring_first.as<int32_t>(),
-                                g->range_off.as<uint64_t>(), g->win.as<uint32_t>(),
-                                g->sorted_keys, roff, g->ranges.as<uint32_t>(),
-                                g->nranges.as<uint32_t>(), g->ncand.as<uint64_t>(), st),
-         "tile ranges");
+  const uint64_t* range_off = g->range_off.as<uint64_t>();
+  const uint32_t* ranges = g->ranges.as<uint32_t>();
+  if (g->lookup == CG_LOOKUP_DISK) {
+    s = run_disk_lookup(g, n, st);
+    if (s != CG_OK) return s;
+    range_off = g->dk_range_off.as<uint64_t>();
+    ranges = g->dk_ranges.as<uint32_t>();
+  } else {
+    CG_HIP(cg::launch_tile_ranges(g->ntiles, g->ring_first.as<int32_t>(),
+                                  g->range_off.as<uint64_t>(), g->win.as<uint32_t>(),
+                                  g->sorted_keys, roff, g->ranges.as<uint32_t>(),
+                                  g->nranges.as<uint32_t>(), g->ncand.as<uint64_t>(), st),
+           "tile ranges");
+  }
   CG_HIP(cg::scan_u64(g->ncand.as<uint64_t>(), g->cand_off.as<uint64_t>(), g->ntiles, st),
          "scan candidates");
   CG_HIP(hipMemcpyAsync(g->h_word, g->cand_off.as<uint64_t>() + g->ntiles, sizeof(uint64_t),
@@ -64,8 +190,7 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
     CG_HIP(ensure(g->cxyz, sizeof(double) * 3 * tc), "alloc candidates");
     g->ncap = tc;
   }
-  CG_HIP(cg::launch_expand(g->range_off.as<uint64_t>(), g->ranges.as<uint32_t>(),
-                           g->nranges.as<uint32_t>(), g->cand_off.as<uint64_t>(), g->ntiles,
+  CG_HIP(cg::launch_expand(range_off, ranges, g->nranges.as<uint32_t>(), g->cand_off.as<uint64_t>(), g->ntiles,
                            g->sorted_vals, g->sx.as<double>(), n, g->cand.as<uint32_t>(),
                            g->crow.as<uint32_t>(), g->cxyz.as<double>(), g->ncap, full_records,
                            st),
@@ -380,6 +505,22 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
   g->nside = nside;
   g->kernel_set = true;
   g->span_valid = false;
+  g->disk_valid = false;
+  return CG_OK;
+}
+
+cg_status cg_set_lookup(cg_gridder* g, int32_t lookup) {
+  if (!g) return fail(CG_E_INVALID, "null handle");
+  if (lookup != CG_LOOKUP_TILES && lookup != CG_LOOKUP_DISK)
+    return fail(CG_E_INVALID, "unknown lookup %d", lookup);
+  g->lookup = lookup;
+  return CG_OK;
+}
+
+cg_status cg_disk_stats(const cg_gridder* g, int64_t* pixels, int64_t* pairs) {
+  if (!g || !pixels || !pairs) return fail(CG_E_INVALID, "null argument");
+  *pixels = g->last_upix;
+  *pairs = g->last_pairs;
   return CG_OK;
 }
 
@@ -390,6 +531,7 @@ cg_status cg_set_nside(cg_gridder* g, int64_t nside) {
   g->nside = nside;
   g->nside_fixed = true;
   g->span_valid = false;
+  g->disk_valid = false;
   return CG_OK;
 }
 
@@ -591,7 +733,11 @@ void cg_destroy(cg_gridder* g) {
                     &g->ring_first, &g->span_bound, &g->range_off, &g->win, &g->S, &g->W, &g->Wn, &g->flag, &g->zrow,
                     &g->keys, &g->vals, &g->keys2, &g->vals2, &g->hist, &g->ring_off, &g->sx,
                     &g->sdata, &g->ranges, &g->nranges, &g->ncand, &g->cand_off, &g->cand,
-                    &g->crow, &g->cxyz};
+                    &g->crow, &g->cxyz, &g->rec, &g->ktab, &g->dk_tkeys, &g->dk_tvals,
+                    &g->dk_tkeys2, &g->dk_tvals2, &g->dk_thist, &g->dk_troff, &g->dk_tab,
+                    &g->dk_flag, &g->dk_uoff, &g->dk_upix, &g->dk_ustart, &g->dk_cnt,
+                    &g->dk_off, &g->dk_pk, &g->dk_pv, &g->dk_pk2, &g->dk_pv2, &g->dk_phist,
+                    &g->dk_rsx, &g->dk_ranges, &g->dk_range_off, &g->dk_scan};
   for (DevBuf* b : bufs) b->release();
   if (g->h_word) (void)hipHostFree(g->h_word);
   delete g;
@@ -668,6 +814,43 @@ cg_status cg_hpx_cap_ranges(int64_t nside, double lon_deg, double lat_deg, doubl
     }
   }
   *nranges = k;
+  return CG_OK;
+}
+
+cg_status cg_hpx_query_disk(int64_t nside, int64_t pix, double support_deg, int64_t* ranges,
+                            int64_t max_ranges, int64_t* nranges) {
+  if (nside < 1 || nside > 8192 || (nside & (nside - 1)) != 0 || pix < 0 ||
+      pix >= cg::hpx::npix(nside) || !ranges || !nranges || !(support_deg > 0.0) ||
+      !(support_deg < 90.0))
+    return fail(CG_E_INVALID, "bad arguments");
+  const double rs = support_deg * kDeg;
+  const int64_t reach = cg::hpx::disk_ring_reach(nside, rs);
+  int64_t i, j;
+  cg::hpx::pix2ring(nside, pix, &i, &j);
+  const int64_t n1 = cg::hpx::ring_npix(nside, i);
+  const int64_t k = j - cg::hpx::ring_ref_pixel(nside, i);
+  int64_t m = 0;
+  for (int64_t i2 = i - reach; i2 <= i + reach; ++i2) {
+    if (i2 < 1 || i2 >= 4 * nside) continue;
+    const int64_t n2 = cg::hpx::ring_npix(nside, i2);
+    int64_t lo = 0, hi = 0, a[2], b[2];
+    const int r = cg::hpx::ref_disk_window(nside, i, i2, rs, &lo, &hi);
+    if (r == 0) continue;
+    int nr = 1;
+    if (r == 2) {
+      a[0] = cg::hpx::ring_start(nside, i2);
+      b[0] = a[0] + n2 - 1;
+    } else {
+      nr = cg::hpx::shifted_window(nside, i2, lo, hi, cg::hpx::disk_shift(k, n2, n1), a, b);
+    }
+    for (int q = 0; q < nr; ++q) {
+      if (m >= max_ranges) return fail(CG_E_INVALID, "max_ranges too small");
+      ranges[2 * m] = a[q];
+      ranges[2 * m + 1] = b[q];
+      ++m;
+    }
+  }
+  *nranges = m;
   return CG_OK;
 }
 

@@ -108,6 +108,16 @@ struct cg_gridder {
   int64_t last_n = 0;
   int64_t last_ncand = 0;
   int64_t ncap = 1;
+  // sample-centric lookup (query disks shifted along rings)
+  int lookup = CG_LOOKUP_TILES;
+  bool disk_valid = false;
+  int64_t disk_reach = 0;
+  cgh::DevBuf dk_tkeys, dk_tvals, dk_tkeys2, dk_tvals2, dk_thist, dk_troff, dk_tab;
+  const uint32_t* dk_tk = nullptr;   // targets sorted by pixel: keys, slots
+  const uint32_t* dk_ts = nullptr;
+  cgh::DevBuf dk_flag, dk_uoff, dk_upix, dk_ustart, dk_cnt, dk_off, dk_pk, dk_pv, dk_pk2, dk_pv2,
+      dk_phist, dk_rsx, dk_ranges, dk_range_off, dk_scan;
+  int64_t last_pairs = 0, last_upix = 0;
   uint64_t* h_word = nullptr;  // pinned host word
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;

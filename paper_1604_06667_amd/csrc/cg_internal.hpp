@@ -186,6 +186,10 @@ hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int6
                           int64_t nchan, bool with_data, int npack, int64_t cap, double* sx,
                           float* sdata, hipStream_t st);
 hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st);
+// the same over many blocks; scratch holds scan_u64_wide_scratch(n) values
+size_t scan_u64_wide_scratch(int64_t n);
+hipError_t scan_u64_wide(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* scratch,
+                         hipStream_t st);
 
 hipError_t launch_wcs_targets(const WcsDev& w, int64_t tile_w, int64_t tile_h, int64_t ntx,
                               int64_t nslots, double* txyz, double* tll, int32_t* slot_target,
@@ -208,6 +212,25 @@ hipError_t launch_tile_windows(const double* caps, const double* txyz, int64_t n
                                int64_t ntiles, int64_t nside, double rho,
                                const int32_t* ring_first, const uint64_t* range_off,
                                uint32_t* win, hipStream_t st);
+// sample-centric lookup (cg_disk.hip)
+hipError_t launch_target_keys(const double* txyz, int64_t nslots, int64_t nside, uint32_t* keys,
+                              uint32_t* vals, hipStream_t st);
+hipError_t launch_ref_disks(int64_t nside, int64_t reach, double rs, int2* tab, hipStream_t st);
+hipError_t launch_run_flags(const uint32_t* keys, const uint32_t* nvalid, int64_t n,
+                            uint64_t* flag, hipStream_t st);
+hipError_t launch_run_compact(const uint32_t* keys, const uint32_t* nvalid, int64_t n,
+                              const uint64_t* uoff, uint32_t* upix, uint32_t* ustart,
+                              hipStream_t st);
+hipError_t launch_disk_pairs(bool count, const uint32_t* upix, int64_t nu, int64_t nside,
+                             int64_t reach, const int2* tab, const uint32_t* tkeys,
+                             const uint32_t* tslot, const uint32_t* troff, const uint64_t* off,
+                             uint64_t* cnt, uint32_t* pk, uint32_t* pv, hipStream_t st);
+hipError_t launch_disk_ranges(const uint32_t* pk, const uint32_t* pv, int64_t np,
+                              const uint32_t* ustart, uint64_t* flag, uint64_t* rsx,
+                              uint64_t* scan_scratch,
+                              int64_t ntiles, uint32_t* ranges, uint64_t* range_off,
+                              uint32_t* nranges, uint64_t* ncand, hipStream_t st);
+
 hipError_t launch_tile_ranges(int64_t ntiles, const int32_t* ring_first,
                               const uint64_t* range_off, const uint32_t* win,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,

@@ -591,4 +591,79 @@ hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st
   return hipGetLastError();
 }
 
+// Device-wide exclusive scan for long arrays: blocks of kScanBlock values
+// are summed, the block sums scanned by k_scan_u64, then every block scans
+// its own values on top of its offset.
+constexpr int kScanBlock = 4096;
+
+__global__ void __launch_bounds__(1024) k_scan_partials(const uint64_t* __restrict__ in, int64_t n,
+                                                        uint64_t* __restrict__ part) {
+  __shared__ uint64_t red[1024];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + 4 * (int64_t)t + k;
+    if (i < n) s += in[i];
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) red[t] += red[t + off];
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(const uint64_t* __restrict__ in,
+                                                     uint64_t* __restrict__ out, int64_t n,
+                                                     const uint64_t* __restrict__ poff,
+                                                     int64_t nb) {
+  __shared__ uint64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  uint64_t v[4];
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + 4 * (int64_t)t + k;
+    v[k] = i < n ? in[i] : 0ull;
+    s += v[k];
+  }
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint64_t u = t >= off ? part[t - off] : 0ull;
+    __syncthreads();
+    part[t] += u;
+    __syncthreads();
+  }
+  uint64_t run = poff[blockIdx.x] + part[t] - s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + 4 * (int64_t)t + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == 0 && t == 0) out[n] = poff[nb];
+}
+
+size_t scan_u64_wide_scratch(int64_t n) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  return (size_t)(2 * nb + 1);
+}
+
+hipError_t scan_u64_wide(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* scratch,
+                         hipStream_t st) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb <= 1) return scan_u64(in, out, n, st);
+  uint64_t* part = scratch;
+  uint64_t* poff = scratch + nb;
+  hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(1024), 0, st, in, n, part);
+  hipLaunchKernelGGL(k_scan_u64, dim3(1), dim3(1024), 0, st, part, poff, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(1024), 0, st, in, out, n, poff, nb);
+  return hipGetLastError();
+}
+
 }  // namespace cg

@@ -493,5 +493,132 @@ CG_HD void pix_centre(int64_t nside, int64_t p, bool nested, double* lon_deg, do
   ring_pixel_centre(nside, i, j, lon_deg, lat_deg);
 }
 
+// ---------------------------------------------------------------------------
+// Query disks shifted along rings (Sect. 3.3, Eq. 4-5): the sample-centric
+// lookup computes one disk per ring, around the ring's reference pixel, and
+// moves it to every other pixel of the ring by integer index shifts.
+
+// z and sin(theta) of the centre of ring i (0 and 4 nside give the poles);
+// cap rings form 1 - |z| directly, as in ring_pixel_centre.
+CG_HD void ring_zs(int64_t nside, int64_t i, double* z, double* st) {
+  if (i <= 0 || i >= 4 * nside) {
+    *z = i <= 0 ? 1.0 : -1.0;
+    *st = 0.0;
+    return;
+  }
+  const double ns = (double)nside;
+  if (i < nside || i > 3 * nside) {
+    const int64_t ic = i < nside ? i : 4 * nside - i;
+    const double omz = (double)(ic * ic) / (3.0 * ns * ns);
+    *z = i < nside ? 1.0 - omz : omz - 1.0;
+    *st = sqrt(omz * (2.0 - omz));
+  } else {
+    *z = (double)(2 * nside - i) * 2.0 / (3.0 * ns);
+    *st = sqrt((1.0 - *z) * (1.0 + *z));
+  }
+}
+
+// Largest angular distance from the centre of a pixel of ring i to any point
+// of that pixel.  Every such point lies in the latitude band
+// [z(i+1), z(i-1)] within half a pixel width of the centre's longitude (the
+// box used by ring_window_ranges); the distance grows with the longitude
+// offset and, along a meridian, is largest at an end of the band, so the
+// box's corners bound it.  Widened by a relative 1e-9 for rounding.
+CG_HD double ring_pixel_radius(int64_t nside, int64_t i) {
+  double z, st;
+  ring_zs(nside, i, &z, &st);
+  const double ch = cos(kPi / (double)ring_npix(nside, i));   // half a pixel width
+  double m = 1.0;
+  for (int e = -1; e <= 1; e += 2) {
+    double z2, s2;
+    ring_zs(nside, i + e, &z2, &s2);
+    const double c = z * z2 + st * s2 * ch;
+    m = c < m ? c : m;
+  }
+  m = m < -1.0 ? -1.0 : m;
+  return acos(m) * (1.0 + 1e-9) + 1e-12;
+}
+
+// The reference pixel of ring i: the one whose centre is nearest longitude
+// pi; on rings with a centre half a pixel either side of pi, the east one.
+CG_HD int64_t ring_ref_pixel(int64_t nside, int64_t i) { return ring_npix(nside, i) / 2; }
+
+// Eq. 4: the shift, in pixels of a ring of n2 pixels, that moves a point by
+// k pixels of a ring of n1 pixels (an angle of k 2 pi / n1), rounded to the
+// nearest integer with halves away from zero.  Exact integer arithmetic.
+CG_HD int64_t disk_shift(int64_t k, int64_t n2, int64_t n1) {
+  const int64_t num = k * n2;
+  const int64_t a = num < 0 ? -num : num;
+  const int64_t q = (2 * a + n1) / (2 * n1);
+  return num < 0 ? -q : q;
+}
+
+// Query disk of the reference pixel of ring i, restricted to ring i2: the
+// window [*lo, *hi] of pixel positions in ring i2 (unwrapped: it may start
+// below 0 or end past the ring's last pixel) whose centres lie within
+// rd = rs + R(i) + R(i2) + 1e-9 of the reference centre (R = ring_pixel_radius,
+// so a sample and a target less than rs apart always have their pixels'
+// centres within rd), widened by one pixel on each side so that it still
+// holds the disk after the rounded shift of Eq. 4.  Returns 0 when the ring
+// misses the disk, 1 for a window, 2 for the whole ring.
+CG_HD int ref_disk_window(int64_t nside, int64_t i, int64_t i2, double rs, int64_t* lo,
+                          int64_t* hi) {
+  const int64_t n1 = ring_npix(nside, i), n2 = ring_npix(nside, i2);
+  const double rd = rs + ring_pixel_radius(nside, i) + ring_pixel_radius(nside, i2) + 1e-9;
+  if (rd >= kPi) return 2;
+  double zc, sc, z, s;
+  ring_zs(nside, i, &zc, &sc);
+  ring_zs(nside, i2, &z, &s);
+  const double den = sc * s;
+  const double arg = (cos(rd) - zc * z) / den;
+  if (arg > 1.0) return 0;
+  if (arg <= -1.0) return 2;
+  const double dphi = acos(arg);
+  const double phc = ((double)ring_ref_pixel(nside, i) + ring_phase(nside, i)) * kTwoPi / (double)n1;
+  const double scale = (double)n2 / kTwoPi, ph = ring_phase(nside, i2);
+  const int64_t a = (int64_t)ceil((phc - dphi) * scale - ph) - 1;
+  const int64_t b = (int64_t)floor((phc + dphi) * scale - ph) + 1;
+  if (b - a + 1 >= n2) return 2;
+  *lo = a;
+  *hi = b;
+  return 1;
+}
+
+// Eq. 5 applied to a window: the positions [lo, hi] of ring i2 moved by dp
+// pixels, wrapped around the ring, as one or two RING index ranges
+// [a[k], b[k]].  Requires hi - lo + 1 < the ring's pixel count.
+CG_HD int shifted_window(int64_t nside, int64_t i2, int64_t lo, int64_t hi, int64_t dp,
+                         int64_t a[2], int64_t b[2]) {
+  const int64_t n = ring_npix(nside, i2), s0 = ring_start(nside, i2);
+  int64_t x = (lo + dp) % n;
+  if (x < 0) x += n;
+  const int64_t y = x + (hi - lo);
+  if (y < n) {
+    a[0] = s0 + x;
+    b[0] = s0 + y;
+    return 1;
+  }
+  a[0] = s0 + x;
+  b[0] = s0 + n - 1;
+  a[1] = s0;
+  b[1] = s0 + (y - n);
+  return 2;
+}
+
+// Rings a shifted query disk can reach on either side of its own ring: the
+// ring centres lie at least 2 / (3 nside) apart in colatitude (the belt's
+// spacing; cap rings are further apart), so a disk of radius rd spans at
+// most 1.5 rd nside + 1 rings each way.  Host-side helper.
+inline int64_t disk_ring_reach(int64_t nside, double rs) {
+  double rmax = 0.0;
+  for (int64_t i = 1; i < 4 * nside; ++i) {
+    const double r = ring_pixel_radius(nside, i);
+    rmax = r > rmax ? r : rmax;
+  }
+  const double rd = rs + 2.0 * rmax + 1e-9;
+  int64_t d = (int64_t)ceil(1.5 * rd * (double)nside) + 2;
+  return d < 4 * nside ? d : 4 * nside;
+}
+
 }  // namespace hpx
 }  // namespace cg
