@@ -107,14 +107,16 @@ typedef enum cg_lookup {
 } cg_lookup;
 
 /* FITS/WCS projections (Calabretta & Greisen 2002): CAR and SFL
- * (Sanson-Flamsteed, Listing 1) non-oblique; SIN and ZEA (zenithal
- * equal-area, Fig. 1) zenithal with LONPOLE = 180 deg. */
+ * (Sanson-Flamsteed, Listing 1) cylindrical, also oblique; SIN and ZEA
+ * (zenithal equal-area, Fig. 1) zenithal with LONPOLE = 180 deg. */
 typedef enum cg_proj { CG_PROJ_CAR = 0, CG_PROJ_SIN = 1, CG_PROJ_SFL = 2, CG_PROJ_ZEA = 3 } cg_proj;
 
 /* Target grid of a WcsGrid: the subset of a FITS/WCS header that defines the
- * pixel centres (Listing 1).  CAR and SFL require crval2 == 0
- * (non-oblique); SIN and ZEA use LONPOLE = 180 deg.  Pixel (i, j) is 1-based
- * along NAXIS1/NAXIS2. */
+ * pixel centres (Listing 1).  CAR and SFL have their reference point at
+ * native (0, 0); with crval2 != 0 they are oblique, with the default LONPOLE
+ * (0 for crval2 > 0, 180 deg for crval2 < 0) and LATPOLE = +90 deg.  SIN and
+ * ZEA use LONPOLE = 180 deg.  |crval2| <= 90.  Pixel (i, j) is 1-based along
+ * NAXIS1/NAXIS2. */
 typedef struct cg_wcs {
   int32_t proj;          /* cg_proj */
   int32_t reserved;      /* must be 0 */
@@ -130,8 +132,8 @@ typedef struct cg_gridder cg_gridder;   /* opaque handle */
  * centres of `wcs`, with `nchan` >= 1 channels per target, on the current
  * HIP device.  The handle owns its accumulators (S: nchan x targets FP32,
  * W: FP64); they start empty.  Errors: CG_E_INVALID (null pointer, naxis <
- * 1, nchan < 1, zero cdelt), CG_E_UNSUPPORTED (unknown projection, oblique
- * CAR or SFL), CG_E_OOM, CG_E_DEVICE.  Pixels without a world coordinate
+ * 1, nchan < 1, zero cdelt, |crval2| > 90), CG_E_UNSUPPORTED (unknown
+ * projection), CG_E_OOM, CG_E_DEVICE.  Pixels without a world coordinate
  * (outside the projection) are empty targets.  Synchronises the null stream
  * once. */
 cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan);

@@ -279,9 +279,6 @@ cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan) {
         isfinite(wcs->cdelt2) && isfinite(wcs->crpix1) && isfinite(wcs->crpix2) &&
         isfinite(wcs->crval1) && isfinite(wcs->crval2)))
     return fail(CG_E_INVALID, "WCS keywords must be finite with non-zero CDELT");
-  if ((wcs->proj == CG_PROJ_CAR || wcs->proj == CG_PROJ_SFL) && wcs->crval2 != 0.0)
-    return fail(CG_E_UNSUPPORTED, "oblique %s (CRVAL2 != 0) is not supported",
-                wcs->proj == CG_PROJ_CAR ? "CAR" : "SFL");
   if (fabs(wcs->crval2) > 90.0) return fail(CG_E_INVALID, "|CRVAL2| > 90");
   const int64_t nt = wcs->naxis1 * wcs->naxis2;
   if (nt >= (1ll << 31) - 64) return fail(CG_E_UNSUPPORTED, "grid too large");
@@ -297,6 +294,7 @@ cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan) {
   g->wcs.crval2 = wcs->crval2;
   g->wcs.cdelt1 = wcs->cdelt1;
   g->wcs.cdelt2 = wcs->cdelt2;
+  cg::wcs_set_pole(&g->wcs);
   g->ntarget = nt;
   g->nchan = nchan;
   g->ntx = (wcs->naxis1 + g->tile_w - 1) / g->tile_w;
@@ -904,9 +902,7 @@ cg_status cg_wcs_pix2world(const cg_wcs* wcs, int64_t n, const double* i, const 
   if (wcs->proj != CG_PROJ_CAR && wcs->proj != CG_PROJ_SIN && wcs->proj != CG_PROJ_SFL &&
       wcs->proj != CG_PROJ_ZEA)
     return fail(CG_E_UNSUPPORTED, "unknown projection");
-  if ((wcs->proj == CG_PROJ_CAR || wcs->proj == CG_PROJ_SFL) && wcs->crval2 != 0.0)
-    return fail(CG_E_UNSUPPORTED, "oblique %s (CRVAL2 != 0) is not supported",
-                wcs->proj == CG_PROJ_CAR ? "CAR" : "SFL");
+  if (!(fabs(wcs->crval2) <= 90.0)) return fail(CG_E_INVALID, "|CRVAL2| > 90");
   cg::WcsDev w;
   w.proj = wcs->proj;
   w.naxis1 = wcs->naxis1;
@@ -917,6 +913,7 @@ cg_status cg_wcs_pix2world(const cg_wcs* wcs, int64_t n, const double* i, const 
   w.crval2 = wcs->crval2;
   w.cdelt1 = wcs->cdelt1;
   w.cdelt2 = wcs->cdelt2;
+  cg::wcs_set_pole(&w);
   for (int64_t k = 0; k < n; ++k) {
     double lo, la;
     if (cg::wcs_pix2world(w, i[k], j[k], &lo, &la)) {

@@ -409,6 +409,29 @@ def config_proj(proj: str, nchan: int = 2, device="cpu") -> Workload:
                     ("gauss1d", (sigma,)), 3.0 * sigma, hpx_maxres=0.5 * sigma)
 
 
+def config_oblique(proj: str, nchan: int = 2, device="cpu") -> Workload:
+    """Oblique cylindrical maps, 121x81 at 0.5 deg: CAR centred at
+    (250, +70) deg, whose rows reach the north celestial pole, and SFL
+    centred at (40, -60) deg; area-uniform samples over the polar cap beyond
+    |lat| = 30 deg on the map's side, smooth field + point sources, Gaussian
+    kernel sigma 0.5 deg, support 1.5 deg."""
+    g = rng(9 if proj == "CAR" else 10)
+    if proj == "CAR":
+        lon, lat = uniform_box(g, 90000, 0.0, 360.0, 30.0, 90.0)
+        wcs = wcs_car(121, 81, 61.0, 41.0, 250.0, -0.5, 0.5)
+        wcs["crval2"] = 70.0
+    else:
+        lon, lat = uniform_box(g, 90000, 0.0, 360.0, -90.0, -30.0)
+        wcs = wcs_car(121, 81, 61.0, 41.0, 40.0, -0.5, 0.5)
+        wcs["crval2"] = -60.0
+    wcs["proj"] = proj
+    sigma = 0.5
+    data = allsky_field(g, lon, lat, nchan, 200, 3.0 * sigma, device=device)
+    return Workload(f"oblique {proj} map {lon.shape[0]} x 121x81 x {nchan}ch",
+                    lon, lat, data, "f32", {"kind": "wcs", "wcs": wcs},
+                    ("gauss1d", (sigma,)), 3.0 * sigma, hpx_maxres=0.5 * sigma)
+
+
 def config_tiny_grid(nx: int, ny: int, nsamples: int = 3000) -> Workload:
     """A SIN grid of nx x ny pixels at 1' (1x1 up to ragged sizes) at
     (40, -20) deg with uniform samples over the grid plus a 5' margin, two

@@ -168,6 +168,27 @@ def test_extra_projections(proj):
     assert ev <= 1e-4
 
 
+@pytest.mark.parametrize("proj", ["CAR", "SFL"])
+def test_oblique_projections(proj):
+    # oblique cylindrical maps (CRVAL2 = +70 with rows through the north
+    # celestial pole, and -60): the pixel centres come from the rotated
+    # native frame; FP32 and BF16 paths, neighbour sets
+    wl = synth.config_oblique(proj)
+    say(wl.name)
+    ref = oracle.grid_workload(wl)
+    g, R, W, (lon, lat, d) = _run_fp32(wl)
+    _check_values(R, W, ref)
+    counts, hashes = g.neighbour_stats(lon, lat)
+    ref_ns = oracle.neighbour_sets(wl.lon, wl.lat, *oracle.targets_of(wl), wl.support)
+    compare_neighbours(counts, hashes, ref_ns)
+    g.set_precision("bf16")
+    cube, w = g.grid_datacube(lon, lat, d)
+    g.sync()
+    ev = oracle.e_val(flat(cube, wl.nchan), ref["R"], ref["W"])
+    say(f"  bf16 e_val={ev:.2e}")
+    assert ev <= 1e-4
+
+
 def _radial_kernels():
     dmax = 4.5 * ARC
     d = np.linspace(0.0, dmax, 64)

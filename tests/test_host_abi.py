@@ -40,9 +40,8 @@ def test_host_argument_errors():
     assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_INVALID
     w = _cg.CgWcs(0, 0, 10, 10, 1, 1, 0, 0, 1, 1)
     assert L.cg_create_wcs(C.byref(h), C.byref(w), 0) == _cg.E_INVALID
-    w = _cg.CgWcs(0, 0, 10, 10, 1, 1, 0, 5.0, 1, 1)      # oblique CAR
-    assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_UNSUPPORTED
-    assert "oblique" in L.cg_last_error().decode()
+    w = _cg.CgWcs(0, 0, 10, 10, 1, 1, 0, 95.0, 1, 1)     # |CRVAL2| > 90
+    assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_INVALID
     w = _cg.CgWcs(1, 0, 10, 10, 1, 1, 0, 0, 0.0, 1)      # zero CDELT
     assert L.cg_create_wcs(C.byref(h), C.byref(w), 1) == _cg.E_INVALID
     assert L.cg_create_sightlines(C.byref(h), None, None, 5, 1, None) == _cg.E_INVALID
@@ -62,7 +61,7 @@ def test_host_argument_errors():
                           [1.0], [1.0])
     with pytest.raises(cgp.CgError):
         cgp.wcs_pix2world({"NAXIS1": 4, "NAXIS2": 4, "CTYPE1": "RA---SFL", "CDELT1": 1, "CDELT2": 1,
-                           "CRVAL2": 10.0}, [1.0], [1.0])
+                           "CRVAL2": 91.0}, [1.0], [1.0])
 
 
 @pytest.mark.parametrize("hdr", [
@@ -86,6 +85,22 @@ def test_host_argument_errors():
     {"NAXIS": 2, "NAXIS1": 120, "NAXIS2": 120, "CTYPE1": "GLON-ZEA", "CTYPE2": "GLAT-ZEA",
      "CRPIX1": 60.5, "CRPIX2": 60.5, "CRVAL1": 0.0, "CRVAL2": 90.0,
      "CDELT1": -0.05, "CDELT2": 0.05},
+    # oblique cylindrical: north and south reference points, a pole, whole-sky planes
+    {"NAXIS": 2, "NAXIS1": 200, "NAXIS2": 150, "CTYPE1": "RA---CAR", "CTYPE2": "DEC--CAR",
+     "CRPIX1": 100.5, "CRPIX2": 75.5, "CRVAL1": 150.0, "CRVAL2": 40.0,
+     "CDELT1": -0.1, "CDELT2": 0.1},
+    {"NAXIS": 2, "NAXIS1": 361, "NAXIS2": 181, "CTYPE1": "GLON-CAR", "CTYPE2": "GLAT-CAR",
+     "CRPIX1": 181.0, "CRPIX2": 91.0, "CRVAL1": 266.4, "CRVAL2": -28.9,
+     "CDELT1": -1.0, "CDELT2": 1.0},
+    {"NAXIS": 2, "NAXIS1": 100, "NAXIS2": 100, "CTYPE1": "RA---CAR", "CTYPE2": "DEC--CAR",
+     "CRPIX1": 50.5, "CRPIX2": 50.5, "CRVAL1": 10.0, "CRVAL2": 90.0,
+     "CDELT1": -0.2, "CDELT2": 0.2},
+    {"NAXIS": 2, "NAXIS1": 361, "NAXIS2": 181, "CTYPE1": "RA---SFL", "CTYPE2": "DEC--SFL",
+     "CRPIX1": 181.0, "CRPIX2": 91.0, "CRVAL1": 300.0, "CRVAL2": 62.0,
+     "CDELT1": -1.0, "CDELT2": 1.0},
+    {"NAXIS": 2, "NAXIS1": 120, "NAXIS2": 90, "CTYPE1": "RA---SFL", "CTYPE2": "DEC--SFL",
+     "CRPIX1": 60.5, "CRPIX2": 45.5, "CRVAL1": 45.0, "CRVAL2": -70.0,
+     "CDELT1": -0.25, "CDELT2": 0.25},
 ])
 def test_library_wcs_matches_oracle(hdr):
     g = np.random.default_rng(0)

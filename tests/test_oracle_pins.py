@@ -216,6 +216,67 @@ def test_sfl_closed_forms():
     assert np.isnan(lo[0]) and np.isnan(la[0])
 
 
+def _ddeg(lo1, la1, lo2, la2):
+    return np.degrees(vincenty(np.radians(lo1), np.radians(la1), np.radians(lo2), np.radians(la2)))
+
+
+def _world(w, x, y):
+    # pixel increments of one degree about pixel (0, 0): (i, j) = (x, y)
+    return wcs_world(w, np.atleast_1d(np.asarray(x, dtype=float)),
+                     np.atleast_1d(np.asarray(y, dtype=float)))
+
+
+@pytest.mark.parametrize("proj", ["CAR", "SFL"])
+@pytest.mark.parametrize("crval2", [35.0, -50.0, 0.5, 90.0])
+def test_oblique_cylindrical_geometry(proj, crval2):
+    # An oblique cylindrical projection is the plain one in a rotated native
+    # frame: the reference pixel is CRVAL, the native meridian and (CAR) the
+    # native equator through it are great circles true to scale, every row
+    # lies at 90 deg - y from the native pole, and the default LONPOLE puts
+    # the celestial pole on native longitude 0 (CRVAL2 > 0) or 180 deg.
+    w = {"proj": proj, "crpix1": 0.0, "crpix2": 0.0, "cdelt1": 1.0, "cdelt2": 1.0,
+         "crval1": 100.0, "crval2": crval2}
+    lo, la = _world(w, 0.0, 0.0)
+    assert _ddeg(lo[0], la[0], 100.0, crval2) < 1e-10
+    ys = np.array([-80.0, -33.0, -1.0, 2.0, 45.0, 89.0])
+    lo, la = _world(w, np.zeros_like(ys), ys)
+    np.testing.assert_allclose(_ddeg(lo, la, 100.0, crval2), np.abs(ys), atol=1e-9)
+    plo, pla = _world(dict(w, proj="CAR"), 0.0, 90.0)         # the native pole
+    for y in (-60.0, 0.0, 30.0, 75.0):
+        xs = np.linspace(-170.0, 170.0, 9) * (math.cos(math.radians(y)) if proj == "SFL" else 1.0)
+        lo, la = _world(w, xs, np.full_like(xs, y))
+        np.testing.assert_allclose(_ddeg(lo, la, plo[0], pla[0]), 90.0 - y, atol=1e-9)
+    if proj == "CAR":
+        xs = np.array([-150.0, -20.0, 5.0, 120.0])
+        lo, la = _world(w, xs, np.zeros_like(xs))
+        np.testing.assert_allclose(_ddeg(lo, la, 100.0, crval2), np.abs(xs), atol=1e-9)
+    # the celestial pole: native (0 or 180 deg, 90 - |CRVAL2|)
+    t = 90.0 - abs(crval2)
+    p = 0.0 if crval2 > 0 else 180.0
+    x = p * (math.cos(math.radians(t)) if proj == "SFL" else 1.0)
+    lo, la = _world(w, x, t)
+    assert la[0] == pytest.approx(90.0, abs=1e-9)
+    # east is east: a small step along +x near CRVAL increases the longitude
+    lo, la = _world(w, 0.01, 0.0)
+    dl = (lo[0] - 100.0 + 180.0) % 360.0 - 180.0
+    assert dl > 0 or abs(crval2) == 90.0
+
+
+def test_oblique_cylindrical_continuity():
+    # CRVAL2 -> 0 joins the non-oblique form
+    for proj in ("CAR", "SFL"):
+        w = {"proj": proj, "crpix1": 0.0, "crpix2": 0.0, "cdelt1": 1.0, "cdelt2": 1.0,
+             "crval1": 100.0, "crval2": 0.0}
+        x = np.array([-120.0, -3.0, 0.0, 17.0, 100.0])
+        y = np.array([-50.0, 10.0, 0.0, 44.0, 70.0])
+        lo0, la0 = _world(w, x, y)
+        lo1, la1 = _world(dict(w, crval2=1e-9), x, y)
+        ok = np.isfinite(lo0)               # SFL: two of the points lie outside its outline
+        assert np.array_equal(ok, np.isfinite(lo1)) and ok.sum() >= 3
+        np.testing.assert_allclose(la1[ok], la0[ok], atol=1e-8)
+        np.testing.assert_allclose((lo1[ok] - lo0[ok] + 180.0) % 360.0 - 180.0, 0.0, atol=1e-8)
+
+
 def _one_pair(kernel, d_deg, support):
     # one sample d_deg north of the target, value 1: R = 1 and W = w(d)
     out = og.grid_bruteforce(np.array([30.0]), np.array([10.0 + d_deg]), np.ones((1, 1)),
