@@ -10,7 +10,10 @@ benchmark times, on sampled outputs the FP64 oracle computes one by one.
 * HEALPix map (App. A.1: ~47 M samples x 2 -> the nside = 512 pixel
   centres): FP32 path at both poles and across the seam;
 * batched (64 uneven jobs, tuned, replayed from the captured graph): the
-  three largest jobs on central blocks.
+  three largest jobs on central blocks;
+* the sample-centric lookup (query disks shifted with Eq. 4-5) on the cube
+  and the sight lines: neighbour counts and hashes identical to the tile
+  lookup's at every target, and the BF16 path on the sampled blocks.
 
 Bars: e_val <= 2e-3 (matrix-core), <= 1e-6 (FP32); neighbour counts equal
 except for samples within 1e-12 rad of the support edge.
@@ -154,6 +157,35 @@ def test_fullsize_sightlines():
         ev = _ev(cube.t(), wl, tidx, ref)
         say(f"  {prec} e_val={ev:.2e}")
         assert ev <= tol
+
+
+@pytest.mark.parametrize("name", ["cube", "sightlines"])
+def test_fullsize_disk_lookup(name):
+    torch = _torch()
+    if name == "cube":
+        wl = synth.config2(device="cuda:0")
+        tidx = _blocks(600, 600, [(276, 276), (0, 0), (580, 300)], 24)
+    else:
+        wl = synth.config5(device="cuda:0")
+        tl, tb = np.asarray(wl.target["lon"]), np.asarray(wl.target["lat"])
+        tidx = np.nonzero((np.abs(tl - 125.0) < 0.3) & (np.abs(tb - 20.0) < 0.3))[0]
+    say(f"full-size disk lookup {wl.name}")
+    g = make_gridder(wl, "bf16")
+    g.set_output_layout("channel" if name == "cube" else "target")
+    lon, lat, d = to_device(wl)
+    c_tiles, h_tiles = g.neighbour_stats(lon, lat)
+    g.set_lookup("disk")
+    c_disk, h_disk = g.neighbour_stats(lon, lat)
+    assert torch.equal(c_tiles, c_disk) and torch.equal(h_tiles, h_disk)
+    say(f"  neighbour sets equal at all {c_disk.numel()} targets; pixels, pairs = {g.disk_stats()}")
+    ref, sidx = _oracle_on(wl, tidx)
+    _check_counts(wl, c_disk, tidx, ref, sidx)
+    cube, w = g.grid_datacube(lon, lat, d)
+    g.sync()
+    ev = _ev(cube if name == "cube" else cube.t(), wl, tidx, ref)
+    ew = oracle.e_weights(w.reshape(-1)[torch.as_tensor(tidx, device=w.device)].cpu().numpy(), ref["W"])
+    say(f"  bf16 e_val={ev:.2e} e_W={ew:.2e}")
+    assert ev <= TOL_MFMA and ew <= TOL32
 
 
 def test_fullsize_healpix_map():
