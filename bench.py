@@ -145,7 +145,10 @@ def oracle_sample(wl, tidx, margin_deg):
     if lat_hi < 89.9 and lat_lo > -89.9 and half < 180.0:
         sel &= np.abs(sl) <= half
     sidx = np.nonzero(sel)[0]
-    data = wl.data[torch.as_tensor(sidx, device=wl.data.device)].to("cpu", torch.float64).numpy()
+    if isinstance(wl.data, np.ndarray):
+        data = wl.data[sidx].astype(np.float64)
+    else:
+        data = wl.data[torch.as_tensor(sidx, device=wl.data.device)].to("cpu", torch.float64).numpy()
     t0 = time.perf_counter()
     ref = oracle.grid_kdtree(wl.lon[sidx], wl.lat[sidx], data, bl, bb, wl.kernel, wl.support)
     dt = time.perf_counter() - t0
@@ -283,6 +286,40 @@ def run_cube(a, dev):
                     {"samples": wl.nsamples, "targets": ntarget, "channels": wl.nchan,
                      "nside": g.nside, "pairs": pairs, "contributions": contributions,
                      "contraction": headline}, roof, cpu)
+    out.update(extra)
+    return out
+
+
+def run_map(a, dev):
+    """The plain map (20,000 samples x 1 FP64 channel onto 96x96 CAR): launch-
+    and latency-bound, so its absolute step time is the figure of interest."""
+    import torch
+    import synth
+    wl = synth.config1()
+    lon = torch.as_tensor(wl.lon, dtype=torch.float64, device=dev)
+    lat = torch.as_tensor(wl.lat, dtype=torch.float64, device=dev)
+    data = torch.as_tensor(wl.data, dtype=torch.float64, device=dev).contiguous()
+    log(f"workload: {wl.name}")
+    g = make_gridder(wl, dev)
+    g.set_precision("fp32")
+    pairs, contributions = count_contributions(g, lon, lat, wl.nchan)
+    nx, ny = wl.target["wcs"]["naxis1"], wl.target["wcs"]["naxis2"]
+    cube = torch.empty((wl.nchan, ny, nx), dtype=torch.float32, device=dev)
+    weights = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    ms, kms, nl = time_path(g, lon, lat, data, cube, weights, a.steps, a.warmup)
+    log(f"fp32: {ms:.4f} ms/step, contraction kernel {kms:.4f} ms x {nl}")
+    roof = roof_alu(2.0 * contributions + FLOPS_PER_PAIR * pairs, kms, "contraction_map_fp32")
+    roof["alg_bytes"] = int(wl.nsamples * (wl.nchan * 8 + 16) + nx * ny * (wl.nchan * 4 + 4))
+    cpu, extra = None, {}
+    if not a.no_cpu:
+        cpu, errs = cpu_baseline(wl, np.arange(nx * ny), f"all {nx}x{ny} targets", {"fp32": cube})
+        extra["e_val"] = errs
+    out = base_line(a, ("plain map: 20,000 samples x 1 FP64 channel -> 96x96 CAR at 2', "
+                        "gauss1d sigma 1.5', support 4.5', nside 4096"),
+                    contributions / (ms / 1e3), ms, "f32",
+                    {"samples": wl.nsamples, "targets": nx * ny, "channels": wl.nchan,
+                     "nside": g.nside, "pairs": pairs, "contributions": contributions,
+                     "contraction": "fp32"}, roof, cpu)
     out.update(extra)
     return out
 
@@ -510,7 +547,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cube",
-                    choices=["cube", "allsky", "batched", "sightlines", "healpix"])
+                    choices=["cube", "allsky", "batched", "sightlines", "healpix", "map"])
     ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "bf16", "fp16"],
                     help="contraction of the cube workload")
     ap.add_argument("--lookup", default="tiles", choices=["tiles", "disk"],
@@ -546,7 +583,7 @@ def main():
         sys.exit(2)
     dev = "cuda:0"
     run = {"cube": run_cube, "allsky": run_allsky, "batched": run_batched,
-           "sightlines": run_sightlines, "healpix": run_healpix}[a.workload]
+           "sightlines": run_sightlines, "healpix": run_healpix, "map": run_map}[a.workload]
     out = run(a, dev)
     if LOOKUP == "disk" and _GRIDDERS:
         npix, npairs = _GRIDDERS[-1].disk_stats()
