@@ -103,6 +103,31 @@ def test_disk_lookup_nside_and_chunks():
     _check(R, W, ref)
 
 
+def test_disk_lookup_nested_map_radial_kernel():
+    # a NESTED HEALPix map (tiles are 8x8 blocks of one base face) gridded
+    # with a tapered-sinc kernel, FP32 and BF16 paths
+    wl = synth.config_hpx(nside=16)
+    wl.target["order"] = "nested"
+    sigma = wl.kernel[1][0]
+    wl.kernel = ("tapered_sinc", (1.5 * sigma, 4.0 * sigma))   # first sinc zero past the support
+    say(f"{wl.name} nested, tapered sinc")
+    ref = oracle.grid_workload(wl)
+    g, R, W, (lon, lat, d) = _run(wl)
+    _check(R, W, ref)
+    _neighbours(g, wl, lon, lat)
+    _, Rb, Wb, _ = _run(wl, "bf16")
+    _check(Rb, Wb, ref, tol=1e-4)
+
+
+def test_disk_lookup_elliptical_fp32_wide():
+    # elliptical kernel, 48 channels (the wide FP32 gather)
+    wl = synth.config5(nsamples=60_000, ntargets=20_000, box=3.0, nchan=48)
+    say(f"disk lookup fp32 wide: {wl.name}")
+    ref = oracle.grid_workload(wl)
+    _, R, W, _ = _run(wl)
+    _check(R, W, ref)
+
+
 @pytest.mark.parametrize("nx,ny", [(9, 3), (17, 65)])
 def test_disk_lookup_tiny_grids(nx, ny):
     wl = synth.config_tiny_grid(nx, ny)

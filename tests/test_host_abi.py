@@ -49,6 +49,9 @@ def test_host_argument_errors():
     assert L.cg_set_kernel(None, 0, p, 1, 1.0, 1.0) == _cg.E_INVALID
     assert L.cg_grid(None, None, None, None, 1, 1, 1, None) == _cg.E_INVALID
     assert L.cg_set_nside(None, 64) == _cg.E_INVALID
+    assert L.cg_set_lookup(None, 1) == _cg.E_INVALID
+    a, b = C.c_int64(), C.c_int64()
+    assert L.cg_disk_stats(None, C.byref(a), C.byref(b)) == _cg.E_INVALID
     assert L.cg_sync(None, None) == _cg.E_INVALID
     v = C.c_int64()
     assert L.cg_query(None, 0, C.byref(v)) == _cg.E_INVALID
