@@ -432,6 +432,36 @@ def config_oblique(proj: str, nchan: int = 2, device="cpu") -> Workload:
                     ("gauss1d", (sigma,)), 3.0 * sigma, hpx_maxres=0.5 * sigma)
 
 
+def config_max_channels(nchan: int = 65535, nsamples: int = 400) -> Workload:
+    """The largest channel count of the API on a 9x3 SIN grid at 1' at
+    (40, -20) deg: samples uniform over the grid plus a 5' margin, FP32 data
+    1 + 0.1 N(0, 1) (a flat continuum with noise); sigma 1.5', support 4.5'."""
+    g = rng(300)
+    wcs = wcs_sin(9, 3, 5.0, 2.0, 40.0, -20.0, -ARCMIN, ARCMIN)
+    lon = 40.0 + g.uniform(-0.5, 0.5, nsamples) * 19 * ARCMIN
+    lat = -20.0 + g.uniform(-0.5, 0.5, nsamples) * 13 * ARCMIN
+    import torch
+    gen = torch.Generator()
+    gen.manual_seed(300)
+    data = 1.0 + 0.1 * torch.randn((nsamples, nchan), generator=gen, dtype=torch.float32)
+    return Workload(f"max channels {nsamples} x 9x3 SIN x {nchan}ch", lon, lat, data, "f32",
+                    {"kind": "wcs", "wcs": wcs}, ("gauss1d", (1.5 * ARCMIN,)), 4.5 * ARCMIN,
+                    hpx_maxres=0.75 * ARCMIN)
+
+
+def config_wide_support(nsamples: int = 3000) -> Workload:
+    """A whole-sky 12x6 CAR grid of 30 deg pixels with a kernel of sigma
+    20 deg and a 60 deg support (every disk takes whole rings and covers a
+    pole); samples uniform on the sphere, two channels of unit Gaussian
+    noise."""
+    g = rng(301)
+    lon, lat = uniform_sphere(g, nsamples)
+    wcs = wcs_car(12, 6, 6.5, 3.5, 180.0, -30.0, 30.0)
+    data = g.normal(size=(nsamples, 2))
+    return Workload(f"wide support {nsamples} x 12x6 CAR", lon, lat, data, "f64",
+                    {"kind": "wcs", "wcs": wcs}, ("gauss1d", (20.0,)), 60.0, hpx_maxres=10.0)
+
+
 def config_tiny_grid(nx: int, ny: int, nsamples: int = 3000) -> Workload:
     """A SIN grid of nx x ny pixels at 1' (1x1 up to ragged sizes) at
     (40, -20) deg with uniform samples over the grid plus a 5' margin, two

@@ -189,6 +189,39 @@ def test_oblique_projections(proj):
     assert ev <= 1e-4
 
 
+def test_max_channels():
+    # 65535 channels (the API's maximum): 64 channel passes with a ragged
+    # last one, FP32 and BF16-split paths, one-shot and accumulate
+    wl = synth.config_max_channels()
+    say(wl.name)
+    ref = oracle.grid_workload(wl)
+    for prec, tol in (("fp32", TOL32), ("bf16", 1e-4)):
+        g = make_gridder(wl, prec)
+        lon, lat, d = to_device(wl)
+        cube, w = g.grid_datacube(lon, lat, d)
+        g.sync()
+        _check_values(flat(cube, wl.nchan), w.cpu().numpy().astype(np.float64).ravel(), ref, tol)
+        g.grid(lon, lat, d)
+        _check_values(flat(g.get_datacube(), wl.nchan), g.get_weights().cpu().numpy().astype(np.float64).ravel(), ref, tol)
+
+
+@pytest.mark.parametrize("lookup", ["tiles", "disk"])
+def test_wide_support(lookup):
+    # sigma 20 deg, support 60 deg on a whole-sky 30 deg grid: every lookup
+    # window is a whole ring and every support disk holds a pole
+    wl = synth.config_wide_support()
+    say(f"{wl.name}, {lookup} lookup")
+    ref = oracle.grid_workload(wl, method="brute")
+    g = make_gridder(wl, "fp32")
+    g.set_lookup(lookup)
+    lon, lat, d = to_device(wl)
+    g.grid(lon, lat, d)
+    _check_values(flat(g.get_datacube(), wl.nchan), g.get_weights().cpu().numpy().astype(np.float64).ravel(), ref)
+    counts, hashes = g.neighbour_stats(lon, lat)
+    ref_ns = oracle.neighbour_sets(wl.lon, wl.lat, *oracle.targets_of(wl), wl.support)
+    compare_neighbours(counts, hashes, ref_ns)
+
+
 def _radial_kernels():
     dmax = 4.5 * ARC
     d = np.linspace(0.0, dmax, 64)
