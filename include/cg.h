@@ -56,8 +56,18 @@ typedef enum cg_status {
   CG_E_OOM = -3,          /* device allocation failed */
   CG_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
   CG_E_DEVICE = -5,       /* a HIP runtime call failed */
-  CG_E_INPUT = -6         /* device-side input error: non-finite or |lat| > 90 */
+  CG_E_INPUT = -6,        /* device-side input error: non-finite or |lat| > 90 */
+  CG_E_WORKSPACE = -7     /* caller workspace smaller than cg_workspace_size */
 } cg_status;
+
+/* Device memory of the library (cg_set_allocator).  alloc returns `bytes`
+ * of device memory on HIP device `device`, at least 256-byte aligned, or
+ * NULL when it has none; `stream` (a hipStream_t as void*, NULL = the null
+ * stream) is the stream of the call that needs it.  free gives back a block
+ * that alloc returned, with its size; the library calls it only after the
+ * device has finished the work it queued on that block. */
+typedef void* (*cg_alloc_fn)(size_t bytes, int device, void* stream, void* ctx);
+typedef void (*cg_free_fn)(void* ptr, size_t bytes, int device, void* ctx);
 
 /* element type of the sample data handed to cg_grid */
 typedef enum cg_dtype { CG_F64 = 0, CG_F32 = 1, CG_F16 = 2, CG_BF16 = 3 } cg_dtype;
@@ -65,7 +75,8 @@ typedef enum cg_dtype { CG_F64 = 0, CG_F32 = 1, CG_F16 = 2, CG_BF16 = 3 } cg_dty
 /* arithmetic of the channel contraction (Eq. 1); distances and the support
  * test are FP64 and the weight map W is accumulated in FP64 in every mode */
 typedef enum cg_prec {
-  CG_PREC_FP32 = 0,   /* FP32 weights x FP32 data on the vector ALUs, two-level FP64 sums */
+  CG_PREC_FP32 = 0,   /* FP32 weights and FP32 data on the vector ALUs, products and sums in
+                         FP64 (exact products, so the sums do not depend on candidate order) */
   CG_PREC_BF16 = 1,   /* matrix cores (MFMA), BF16 operands, FP32 accumulate: data and weights
                          are split into BF16 high and residual parts and each block is the sum
                          of three products (hi*hi + lo*hi + hi*lo) */
@@ -128,6 +139,19 @@ typedef struct cg_wcs {
 
 typedef struct cg_gridder cg_gridder;   /* opaque handle */
 
+/* Where handles and batches created from now on take their device memory
+ * (PyTorch's caching allocator, a pool, ...): every buffer a handle or batch
+ * owns comes from alloc_fn and goes back through free_fn, with `ctx` passed
+ * through.  A handle keeps the allocator that was in force when it was
+ * created until it is destroyed.  NULL for both restores hipMalloc/hipFree.
+ * Grid calls allocate nothing once a handle is set up, apart from growing
+ * the handle's own workspace when no caller workspace is passed, the
+ * accumulators of the first cg_grid, and the pair lists of the
+ * sample-centric lookup.  A failing alloc_fn makes the call that needed the
+ * memory return CG_E_OOM and leaves the handle usable.  Errors:
+ * CG_E_INVALID (only one of the two functions given). */
+cg_status cg_set_allocator(cg_alloc_fn alloc_fn, cg_free_fn free_fn, void* ctx);
+
 /* WcsGrid(header) (Sect. 3.5): a gridder whose targets are the pixel
  * centres of `wcs`, with `nchan` >= 1 channels per target, on the current
  * HIP device.  The handle owns its accumulators (S: nchan x targets FP32,
@@ -173,13 +197,19 @@ cg_status cg_create_healpix(cg_gridder** out, int64_t nside, int32_t order, int6
  * support < 90).  hpx_maxres_deg: resolution of the internal HEALPix grid;
  * nside = smallest power of two with sqrt(pi/3)/nside <= hpx_maxres (a
  * speed knob only: the support test is exact), unless cg_set_nside fixed
- * it.  May be called again; changing the kernel discards nothing already
- * accumulated.  Errors: CG_E_INVALID. */
+ * it.  Builds the handle's lookup tables for this support (the HEALPix
+ * pixel windows of every tile of targets) on the null stream and waits for
+ * them.  May be called again; changing the kernel discards nothing already
+ * accumulated.  Every argument is checked before anything changes: a
+ * rejected call leaves the previous kernel in force.  Errors:
+ * CG_E_INVALID, CG_E_OOM, CG_E_DEVICE. */
 cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params, int32_t nparams,
                         double support_deg, double hpx_maxres_deg);
 
 /* Fix the internal HEALPix nside (power of two, 1 <= nside <= 8192) instead of
- * deriving it from hpx_maxres.  Errors: CG_E_INVALID. */
+ * deriving it from hpx_maxres.  After cg_set_kernel it rebuilds the lookup
+ * tables as cg_set_kernel does.  Errors: CG_E_INVALID, CG_E_OOM,
+ * CG_E_DEVICE. */
 cg_status cg_set_nside(cg_gridder* g, int64_t nside);
 
 /* Select the lookup (cg_lookup) of this handle's grid, grid_datacube and
@@ -209,17 +239,35 @@ cg_status cg_set_precision(cg_gridder* g, int32_t prec);
  * CG_E_INVALID. */
 cg_status cg_set_output_layout(cg_gridder* g, int32_t layout);
 
+/* Bytes of device workspace a grid call (cg_grid, cg_grid_datacube) on
+ * `nsamples` samples needs with the handle's current kernel, nside and
+ * precision: the HEALPix keys with their sort buffers, the ring offsets, the
+ * sorted unit vectors and sample records, and for FP32 grids of at most 16
+ * channels the sorted data rows.  About 72 bytes per sample plus 4 * nchan
+ * per sample in that last case.  Errors: CG_E_INVALID, CG_E_STATE (no
+ * kernel set). */
+cg_status cg_workspace_size(const cg_gridder* g, int64_t nsamples, size_t* bytes);
+
 /* grid(lon, lat, signal) (Listing 1; Sect. 2.1 Eq. 1-2): add the
  * contributions of `nsamples` samples to S and W.  lon_deg, lat_deg: device
  * FP64 [nsamples].  data: device, `dtype` elements, row n at data + n*ld_data
  * elements, channel c at column c (one spectrum contiguous); ld_data >=
- * nchan.  Repeated calls accumulate (chunked input equals one call).
- * Samples with non-finite or |lat| > 90 coordinates are skipped and set the
- * sticky input flag reported by cg_sync.  nsamples == 0 is a no-op.
- * Synchronises `stream` once to size the candidate lists.  Errors:
- * CG_E_STATE (no kernel set), CG_E_INVALID, CG_E_OOM, CG_E_DEVICE. */
+ * nchan.  Repeated calls accumulate in FP64 (chunked input equals one call
+ * to rounding of the sums).  Samples with non-finite or |lat| > 90
+ * coordinates are skipped and set the sticky input flag reported by
+ * cg_sync.  nsamples == 0 is a no-op.
+ * ws, ws_bytes: device workspace of at least cg_workspace_size bytes,
+ * 256-byte aligned, owned by the caller and not touched after the queued
+ * work completes (it may be reused for the next call on the same stream);
+ * NULL: the handle uses (and if needed grows) a workspace of its own.
+ * With the tile lookup the call only queues device work: it neither waits
+ * for the device nor (given a workspace) allocates, except for the
+ * accumulators (FP64 [nchan][targets]) on the first cg_grid of a handle.
+ * Errors: CG_E_STATE (no kernel set), CG_E_INVALID, CG_E_WORKSPACE,
+ * CG_E_OOM, CG_E_DEVICE. */
 cg_status cg_grid(cg_gridder* g, const double* lon_deg, const double* lat_deg, const void* data,
-                  int32_t dtype, int64_t nsamples, int64_t ld_data, void* stream);
+                  int32_t dtype, int64_t nsamples, int64_t ld_data, void* ws, size_t ws_bytes,
+                  void* stream);
 
 /* get_datacube() (Listing 1; Eq. 3): out = device FP32 [nchan][naxis2][naxis1]
  * for a WCS grid (FITS/numpy order) or [nchan][ntarget] for sight lines;
@@ -234,10 +282,13 @@ cg_status cg_get_weights(cg_gridder* g, float* out, void* stream);
 /* clear + grid + get_datacube + get_weights in one pass: the accumulators are
  * left empty and the normalised cube and weight map are written straight to
  * cube_out / weights_out (layouts as above; weights_out may be NULL).  Same
- * argument rules and errors as cg_grid. */
+ * argument rules, workspace and errors as cg_grid; with the tile lookup and
+ * a caller workspace it queues device work only (no allocation, no wait),
+ * so it can be captured into a HIP graph. */
 cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* lat_deg,
                            const void* data, int32_t dtype, int64_t nsamples, int64_t ld_data,
-                           float* cube_out, float* weights_out, void* stream);
+                           float* cube_out, float* weights_out, void* ws, size_t ws_bytes,
+                           void* stream);
 
 /* Reset S and W to empty (Sect. 2.1 step 1). */
 cg_status cg_clear(cg_gridder* g, void* stream);
@@ -257,7 +308,8 @@ cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double*
                              int64_t nsamples, int32_t* counts, uint64_t* hashes, void* stream);
 
 /* Handle queries (host):  what = 0 ntargets, 1 nchan, 2 nside, 3 ntiles,
- * 4 candidates in the last grid call, 5 precision, 6 device, 7 layout. */
+ * 4 candidates of the last lookup (waits for the device), 5 precision,
+ * 6 device, 7 layout. */
 cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value);
 
 /* Measurement: while enabled, every launch of the contraction kernel (the
@@ -308,8 +360,9 @@ typedef struct cg_batch_job {
 cg_status cg_batch_create(cg_batch** out, cg_gridder* const* jobs, int32_t njobs, int32_t dtype);
 
 /* One pass over all jobs: in[njobs] (host array of device pointers).  Writes
- * every job's cube and weights.  Synchronises `stream` once to size the
- * candidate lists.  Invalid sample coordinates are skipped and reported by
+ * every job's cube and weights.  Buffers are sized from the sample counts;
+ * the call waits for the device only before it reuses its pinned staging of
+ * the job table.  Invalid sample coordinates are skipped and reported by
  * cg_batch_sync.  Errors: CG_E_INVALID, CG_E_OOM, CG_E_DEVICE. */
 cg_status cg_batch_grid(cg_batch* b, const cg_batch_job* in, void* stream);
 
@@ -323,25 +376,23 @@ cg_status cg_batch_tune(cg_batch* b, const cg_batch_job* in, int32_t reps, void*
 
 /* Record one cg_batch_grid step on `in` as a HIP graph (after running it
  * once eagerly to size every buffer), for replay by cg_batch_replay without
- * host synchronisation.  The graph keeps the device pointers of `in` and the
- * candidate capacity of the eager run; a replay whose samples need more
- * candidates writes nothing and is reported by cg_batch_sync (capture
- * again).  A later cg_batch_grid that must enlarge a buffer, or
- * cg_batch_tune, drops the graph.  Waits for the device.  Errors as
- * cg_batch_grid. */
+ * host synchronisation.  The graph keeps the device pointers and sample
+ * counts of `in`: a replay grids whatever those buffers hold when it runs.
+ * A later cg_batch_grid that must enlarge a buffer, or cg_batch_tune, drops
+ * the graph.  Waits for the device.  Errors as cg_batch_grid. */
 cg_status cg_batch_capture(cg_batch* b, const cg_batch_job* in, void* stream);
 
 /* Launch the captured graph on `stream`.  Errors: CG_E_STATE (no graph),
  * CG_E_DEVICE. */
 cg_status cg_batch_replay(cg_batch* b, void* stream);
 
-/* Wait for `stream`; CG_E_INPUT if an invalid sample coordinate was seen,
- * CG_E_STATE if a replay exceeded the captured candidate capacity (both
- * flags are then cleared), CG_E_DEVICE on a HIP failure, else CG_OK. */
+/* Wait for `stream`; CG_E_INPUT if an invalid sample coordinate was seen
+ * (the flag is then cleared), CG_E_DEVICE on a HIP failure, else CG_OK. */
 cg_status cg_batch_sync(cg_batch* b, void* stream);
 
 /* Batch queries (host): what = 0 njobs, 1 samples of the last pass,
- * 2 tiles, 3 work items, 4 candidates of the last eager pass, 5 matrix rows
+ * 2 tiles, 3 work items, 4 candidates of the last pass (waits for the
+ * device), 5 matrix rows
  * per workgroup (128-512), 6 half-width items (0/1), 7 workgroups per
  * compute unit, 8 graph captured (0/1), 9 workgroup shape (0-3). */
 cg_status cg_batch_query(const cg_batch* b, int32_t what, int64_t* value);

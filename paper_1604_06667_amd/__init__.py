@@ -10,4 +10,5 @@ library.
 from ._cg import (WcsGrid, SlGrid, HpxGrid, Batch, CgError, lib, version, parse_header,  # noqa: F401
                   hpx_ang2pix_ring, hpx_pix2ang_ring, hpx_pix2ring, hpx_ring_info,
                   hpx_cap_ranges, hpx_targets_ranges, hpx_query_disk, hpx_centres,
-                  wcs_pix2world, PREC, KERNEL, HPX_ORDER, LOOKUP)
+                  wcs_pix2world, set_allocator, use_torch_allocator, PREC, KERNEL, HPX_ORDER,
+                  LOOKUP)

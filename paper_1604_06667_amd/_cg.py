@@ -13,7 +13,8 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcg.so")
 
-OK, E_INVALID, E_STATE, E_OOM, E_UNSUPPORTED, E_DEVICE, E_INPUT = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVALID, E_STATE, E_OOM, E_UNSUPPORTED, E_DEVICE, E_INPUT, E_WORKSPACE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
 F64, F32, F16, BF16 = 0, 1, 2, 3
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 KERNEL = {"gauss1d": 0, "gauss2d": 1, "tapered_sinc": 2, "table": 3}
@@ -42,8 +43,12 @@ class CgBatchJob(C.Structure):
                 ("cube_out", C.c_void_p), ("weights_out", C.c_void_p)]
 
 
-_vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_vp, _i32, _i64, _d, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
 _P = C.POINTER
+
+# cg_alloc_fn / cg_free_fn (include/cg.h)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
 
 SIGNATURES = {
     "cg_create_wcs": (_i32, [_P(_vp), _P(CgWcs), _i64]),
@@ -56,10 +61,12 @@ SIGNATURES = {
     "cg_set_lookup": (_i32, [_vp, _i32]),
     "cg_disk_stats": (_i32, [_vp, _P(_i64), _P(_i64)]),
     "cg_set_output_layout": (_i32, [_vp, _i32]),
-    "cg_grid": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp]),
+    "cg_set_allocator": (_i32, [ALLOC_FN, FREE_FN, _vp]),
+    "cg_workspace_size": (_i32, [_vp, _i64, _P(_sz)]),
+    "cg_grid": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _sz, _vp]),
     "cg_get_datacube": (_i32, [_vp, _vp, _vp]),
     "cg_get_weights": (_i32, [_vp, _vp, _vp]),
-    "cg_grid_datacube": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp]),
+    "cg_grid_datacube": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp, _sz, _vp]),
     "cg_clear": (_i32, [_vp, _vp]),
     "cg_sync": (_i32, [_vp, _vp]),
     "cg_neighbour_stats": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
@@ -118,6 +125,59 @@ def version() -> str:
     return lib().cg_version().decode()
 
 
+# ------------------------------------------------------------- allocator
+
+_ALLOC = {"mode": None, "fns": None}
+
+
+def _torch_alloc(nbytes, device, stream, ctx):
+    try:
+        torch = _torch()
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device),
+                                                  stream=int(stream) if stream else None)
+    except Exception:   # out of memory: the library reports CG_E_OOM
+        return None
+
+
+def _torch_free(ptr, nbytes, device, ctx):
+    try:
+        _torch().cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+def set_allocator(alloc=None, free=None):
+    """Device memory of gridders and batches created from now on
+    (cg_set_allocator): ``alloc(nbytes, device, stream) -> int`` (a device
+    address, 0 when out of memory) and ``free(ptr, nbytes, device)``, or
+    ``None`` for both to use hipMalloc/hipFree."""
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        fns = (ALLOC_FN(), FREE_FN())
+        _ALLOC["mode"] = "hip"
+    else:
+        fns = (ALLOC_FN(lambda n, d, s, c: alloc(n, d, s) or None),
+               FREE_FN(lambda p, n, d, c: free(p, n, d)))
+        _ALLOC["mode"] = "custom"
+    check(lib().cg_set_allocator(fns[0], fns[1], None))
+    _ALLOC["fns"] = fns   # the callbacks must outlive every handle that uses them
+
+
+def use_torch_allocator():
+    """Give gridders and batches created from now on PyTorch's caching
+    allocator (the default of this binding)."""
+    fns = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
+    check(lib().cg_set_allocator(fns[0], fns[1], None))
+    _ALLOC["fns"] = fns
+    _ALLOC["mode"] = "torch"
+
+
+def _default_allocator():
+    if _ALLOC["mode"] is None:
+        use_torch_allocator()
+
+
 # ------------------------------------------------------------------- helpers
 
 def _torch():
@@ -149,6 +209,16 @@ def _dtype_code(t):
     if t.dtype not in m:
         raise TypeError(f"unsupported data dtype {t.dtype}")
     return m[t.dtype]
+
+
+def _ws_arg(ws):
+    """(pointer, bytes) of a caller workspace tensor, or (NULL, 0)."""
+    if ws is None:
+        return None, 0
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+        raise TypeError("ws must be a contiguous CUDA (HIP) tensor")
+    return C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
 
 
 def _data2d(signal, nchan):
@@ -246,12 +316,26 @@ class _Gridder:
             raise ValueError("lon/lat must be 1-D of equal length")
         return _dev_ptr(lon, torch.float64, "lon"), _dev_ptr(lat, torch.float64, "lat")
 
+    def workspace_size(self, nsamples):
+        """Bytes of workspace a grid call on ``nsamples`` samples needs."""
+        v = C.c_size_t()
+        check(lib().cg_workspace_size(self._handle(), int(nsamples), C.byref(v)))
+        return v.value
+
+    def workspace(self, nsamples):
+        """A device workspace (uint8 tensor) for grid calls on up to
+        ``nsamples`` samples."""
+        torch = _torch()
+        return torch.empty(self.workspace_size(nsamples), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+
     # Listing 1: grid(lon, lat, signal); accumulates
-    def grid(self, lon, lat, signal, stream=None):
+    def grid(self, lon, lat, signal, ws=None, stream=None):
         pl, pb = self._coords(lon, lat)
         sig = _data2d(signal, self.nchan)
+        wp, wn = _ws_arg(ws)
         check(lib().cg_grid(self._handle(), pl, pb, C.c_void_p(sig.data_ptr()), _dtype_code(sig),
-                            int(lon.shape[0]), int(sig.stride(0)), _stream(stream)))
+                            int(lon.shape[0]), int(sig.stride(0)), wp, wn, _stream(stream)))
 
     def _empty_out(self, nch):
         torch = _torch()
@@ -276,7 +360,7 @@ class _Gridder:
         check(lib().cg_get_weights(self._handle(), _dev_ptr(out, name="out"), _stream(stream)))
         return out
 
-    def grid_datacube(self, lon, lat, signal, cube=None, weights=None, stream=None):
+    def grid_datacube(self, lon, lat, signal, cube=None, weights=None, ws=None, stream=None):
         """clear + grid + get_datacube + get_weights in one pass."""
         pl, pb = self._coords(lon, lat)
         sig = _data2d(signal, self.nchan)
@@ -285,9 +369,10 @@ class _Gridder:
         if weights is not False:
             weights = self._empty_out(0) if weights is None else weights
             wp = _dev_ptr(weights, name="weights")
+        sp, sn = _ws_arg(ws)
         check(lib().cg_grid_datacube(self._handle(), pl, pb, C.c_void_p(sig.data_ptr()),
                                      _dtype_code(sig), int(lon.shape[0]), int(sig.stride(0)),
-                                     _dev_ptr(cube, name="cube"), wp, _stream(stream)))
+                                     _dev_ptr(cube, name="cube"), wp, sp, sn, _stream(stream)))
         return cube, (weights if weights is not False else None)
 
     def clear(self, stream=None):
@@ -337,6 +422,7 @@ class WcsGrid(_Gridder):
 
     def __init__(self, header: dict, nchan: int | None = None):
         super().__init__()
+        _default_allocator()
         w, n = parse_header(header)
         self.nchan = int(nchan) if nchan is not None else n
         h = C.c_void_p()
@@ -352,6 +438,7 @@ class SlGrid(_Gridder):
     def __init__(self, lon, lat, nchan: int = 1, stream=None):
         super().__init__()
         torch = _torch()
+        _default_allocator()
         pl = _dev_ptr(lon, torch.float64, "lon")
         pb = _dev_ptr(lat, torch.float64, "lat")
         self.nchan = int(nchan)
@@ -375,6 +462,7 @@ class HpxGrid(_Gridder):
         super().__init__()
         if order not in HPX_ORDER:
             raise ValueError(f"order must be one of {sorted(HPX_ORDER)}")
+        _default_allocator()
         self.nchan = int(nchan)
         self.map_nside = int(nside)     # (nside is the lookup resolution)
         self.map_order = order
@@ -398,6 +486,7 @@ class Batch:
                  torch.bfloat16: BF16}
         if dtype not in codes:
             raise TypeError(f"unsupported data dtype {dtype}")
+        _default_allocator()
         self.gridders = list(gridders)
         self.dtype = dtype
         arr = (C.c_void_p * len(self.gridders))(*[g._handle().value for g in self.gridders])

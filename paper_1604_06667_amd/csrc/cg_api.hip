@@ -7,10 +7,6 @@ using namespace cgh;
 
 bool small_c(const cg_gridder* g) { return g->nchan <= cg::kSmallC && g->prec == CG_PREC_FP32; }
 
-// HEALPix index, sort, ring offsets, permute and candidate lists for n samples.
-// full_records: the matrix-core contraction follows, which reads each
-// candidate's unit vector and input index from per-tile copies; the FP32
-// gathers and the statistics read them from the sorted arrays.
 // Set-up of the sample-centric lookup: targets sorted by their nearest
 // RING pixel with per-ring offsets (the hash table of Sect. 2.2), and the
 // reference query disk of every ring (Sect. 3.3).  Depends only on the
@@ -23,13 +19,13 @@ cg_status ensure_disk(cg_gridder* g, hipStream_t st) {
   if (entries > (int64_t(1) << 28))
     return fail(CG_E_UNSUPPORTED, "query-disk table of %lld entries (support too wide for nside)",
                 (long long)entries);
-  CG_HIP(ensure(g->dk_tkeys, sizeof(uint32_t) * nsl), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_tvals, sizeof(uint32_t) * nsl), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_tkeys2, sizeof(uint32_t) * nsl), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_tvals2, sizeof(uint32_t) * nsl), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_thist, sizeof(uint32_t) * cg::radix_hist_elems(nsl)), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_troff, sizeof(uint32_t) * (4 * nside + 1)), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_tab, sizeof(int2) * entries), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_tkeys, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_tvals, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_tkeys2, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_tvals2, sizeof(uint32_t) * nsl), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_thist, sizeof(uint32_t) * cg::radix_hist_elems(nsl)), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_troff, sizeof(uint32_t) * (4 * nside + 1)), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_tab, sizeof(int2) * entries), "alloc disk lookup");
   CG_HIP(cg::launch_target_keys(g->txyz.as<double>(), nsl, nside, g->dk_tkeys.as<uint32_t>(),
                                 g->dk_tvals.as<uint32_t>(), st),
          "target keys");
@@ -53,19 +49,20 @@ cg_status ensure_disk(cg_gridder* g, hipStream_t st) {
 // Sample-centric candidate ranges of a grid call (after the samples are
 // sorted): distinct sample pixels, their shifted query disks matched with
 // the targets as (tile, pixel) pairs, the pairs sorted by tile, and per tile
-// the merged ranges of sorted samples with their candidate counts.
+// the merged ranges of sorted samples with their candidate counts.  The pair
+// lists are sized on the host, so this lookup waits for the device twice.
 cg_status run_disk_lookup(cg_gridder* g, int64_t n, hipStream_t st) {
   cg_status s = ensure_disk(g, st);
   if (s != CG_OK) return s;
   const int64_t nside = g->nside;
-  const uint32_t* nvalid = g->ring_off.as<uint32_t>() + 4 * nside;
-  CG_HIP(ensure(g->dk_flag, sizeof(uint64_t) * n), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_uoff, sizeof(uint64_t) * (n + 1)), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_upix, sizeof(uint32_t) * n), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_ustart, sizeof(uint32_t) * (n + 1)), "alloc disk lookup");
+  const uint32_t* nvalid = g->ws.ring_off + 4 * nside;
+  CG_HIP(ensure(g->alloc, g->dk_flag, sizeof(uint64_t) * n), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_uoff, sizeof(uint64_t) * (n + 1)), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_upix, sizeof(uint32_t) * n), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_ustart, sizeof(uint32_t) * (n + 1)), "alloc disk lookup");
   CG_HIP(cg::launch_run_flags(g->sorted_keys, nvalid, n, g->dk_flag.as<uint64_t>(), st),
          "pixel runs");
-  CG_HIP(ensure(g->dk_scan, sizeof(uint64_t) * cg::scan_u64_wide_scratch(n)), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_scan, sizeof(uint64_t) * cg::scan_u64_wide_scratch(n)), "alloc disk lookup");
   CG_HIP(cg::scan_u64_wide(g->dk_flag.as<uint64_t>(), g->dk_uoff.as<uint64_t>(), n,
                            g->dk_scan.as<uint64_t>(), st),
          "scan runs");
@@ -77,8 +74,8 @@ cg_status run_disk_lookup(cg_gridder* g, int64_t n, hipStream_t st) {
          "read runs");
   CG_HIP(hipStreamSynchronize(st), "sync runs");
   const int64_t nu = (int64_t)g->h_word[0];
-  CG_HIP(ensure(g->dk_cnt, sizeof(uint64_t) * nu), "alloc disk lookup");
-  CG_HIP(ensure(g->dk_off, sizeof(uint64_t) * (nu + 1)), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_cnt, sizeof(uint64_t) * nu), "alloc disk lookup");
+  CG_HIP(ensure(g->alloc, g->dk_off, sizeof(uint64_t) * (nu + 1)), "alloc disk lookup");
   CG_HIP(cg::launch_disk_pairs(true, g->dk_upix.as<uint32_t>(), nu, nside, g->disk_reach,
                                g->dk_tab.as<int2>(), g->dk_tk, g->dk_ts,
                                g->dk_troff.as<uint32_t>(), nullptr, g->dk_cnt.as<uint64_t>(),
@@ -97,16 +94,16 @@ cg_status run_disk_lookup(cg_gridder* g, int64_t n, hipStream_t st) {
   g->last_upix = nu;
   g->last_pairs = np;
   const int64_t nt = g->ntiles;
-  CG_HIP(ensure(g->dk_pk, sizeof(uint32_t) * np), "alloc pairs");
-  CG_HIP(ensure(g->dk_pv, sizeof(uint32_t) * np), "alloc pairs");
-  CG_HIP(ensure(g->dk_pk2, sizeof(uint32_t) * np), "alloc pairs");
-  CG_HIP(ensure(g->dk_pv2, sizeof(uint32_t) * np), "alloc pairs");
-  CG_HIP(ensure(g->dk_phist, sizeof(uint32_t) * cg::radix_hist_elems(np)), "alloc pairs");
-  CG_HIP(ensure(g->dk_flag, sizeof(uint64_t) * np), "alloc pairs");
-  CG_HIP(ensure(g->dk_rsx, sizeof(uint64_t) * (np + 1)), "alloc pairs");
-  CG_HIP(ensure(g->dk_scan, sizeof(uint64_t) * cg::scan_u64_wide_scratch(np)), "alloc pairs");
-  CG_HIP(ensure(g->dk_ranges, sizeof(uint32_t) * 2 * np), "alloc pairs");
-  CG_HIP(ensure(g->dk_range_off, sizeof(uint64_t) * (nt + 1)), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_pk, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_pv, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_pk2, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_pv2, sizeof(uint32_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_phist, sizeof(uint32_t) * cg::radix_hist_elems(np)), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_flag, sizeof(uint64_t) * np), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_rsx, sizeof(uint64_t) * (np + 1)), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_scan, sizeof(uint64_t) * cg::scan_u64_wide_scratch(np)), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_ranges, sizeof(uint32_t) * 2 * np), "alloc pairs");
+  CG_HIP(ensure(g->alloc, g->dk_range_off, sizeof(uint64_t) * (nt + 1)), "alloc pairs");
   CG_HIP(cg::launch_disk_pairs(false, g->dk_upix.as<uint32_t>(), nu, nside, g->disk_reach,
                                g->dk_tab.as<int2>(), g->dk_tk, g->dk_ts,
                                g->dk_troff.as<uint32_t>(), g->dk_off.as<uint64_t>(), nullptr,
@@ -128,73 +125,47 @@ cg_status run_disk_lookup(cg_gridder* g, int64_t n, hipStream_t st) {
   return CG_OK;
 }
 
+// HEALPix index, sort, ring offsets and permutation of n samples, then the
+// ranges of sorted samples that each tile's lookup finds.  Uses the
+// workspace at `base` (workspace_layout for n samples) and the handle's
+// set-up tables, and only queues device work: with the tile lookup nothing
+// here waits for the device or allocates (the sample-centric lookup sizes
+// and allocates its pair lists per call).
 cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_t n,
-                     const void* data, int32_t dtype, int64_t ld, bool with_data,
-                     bool full_records, hipStream_t st) {
+                     const void* data, int32_t dtype, int64_t ld, bool with_data, char* base,
+                     hipStream_t st) {
   cg_status s = ensure_span(g, st);
   if (s != CG_OK) return s;
   const int64_t nside = g->nside;
-  CG_HIP(ensure(g->keys, sizeof(uint32_t) * n), "alloc keys");
-  CG_HIP(ensure(g->vals, sizeof(uint32_t) * n), "alloc keys");
-  CG_HIP(ensure(g->keys2, sizeof(uint32_t) * n), "alloc keys");
-  CG_HIP(ensure(g->vals2, sizeof(uint32_t) * n), "alloc keys");
-  CG_HIP(ensure(g->hist, sizeof(uint32_t) * cg::radix_hist_elems(n)), "alloc hist");
-  CG_HIP(ensure(g->ring_off, sizeof(uint32_t) * (4 * nside + 1)), "alloc ring offsets");
-  CG_HIP(ensure(g->sx, sizeof(double) * 3 * n), "alloc sorted vectors");
-  if (with_data) CG_HIP(ensure(g->sdata, sizeof(float) * n * g->nchan), "alloc sorted data");
-  CG_HIP(ensure(g->rec, 4 * sizeof(double) * n), "alloc sample records");
+  workspace_layout(n, nside, with_data ? g->nchan : 0, base, &g->ws);
+  Workspace& w = g->ws;
   const int npack = with_data && g->nchan <= 2 ? (int)g->nchan : 0;
-  CG_HIP(cg::launch_prep(lon, lat, n, nside, g->keys.as<uint32_t>(), g->vals.as<uint32_t>(),
-                         g->flag.as<int>(), g->rec.as<double>(), data, dtype, ld, npack, st),
+  CG_HIP(cg::launch_prep(lon, lat, n, nside, w.keys, w.vals, g->flag.as<int>(), w.rec, data,
+                         dtype, ld, npack, st),
          "prep");
   bool in_tmp = false;
   const int bits = bits_for((uint64_t)cg::hpx::npix(nside));
-  CG_HIP(cg::radix_sort(g->keys.as<uint32_t>(), g->vals.as<uint32_t>(), g->keys2.as<uint32_t>(),
-                        g->vals2.as<uint32_t>(), g->hist.as<uint32_t>(), n, bits, &in_tmp, st),
+  CG_HIP(cg::radix_sort(w.keys, w.vals, w.keys2, w.vals2, w.hist, n, bits, &in_tmp, st),
          "radix sort");
-  g->sorted_keys = in_tmp ? g->keys2.as<uint32_t>() : g->keys.as<uint32_t>();
-  g->sorted_vals = in_tmp ? g->vals2.as<uint32_t>() : g->vals.as<uint32_t>();
-  uint32_t* roff = g->ring_off.as<uint32_t>();
-  CG_HIP(cg::launch_ring_offsets(g->sorted_keys, n, nside, roff, st), "ring offsets");
-  CG_HIP(cg::launch_permute(g->sorted_vals, roff + 4 * nside, n, g->rec.as<double>(), data, dtype,
-                            ld, g->nchan, with_data, npack, n, g->sx.as<double>(),
-                            g->sdata.as<float>(), st),
+  g->sorted_keys = in_tmp ? w.keys2 : w.keys;
+  g->sorted_vals = in_tmp ? w.vals2 : w.vals;
+  CG_HIP(cg::launch_ring_offsets(g->sorted_keys, n, nside, w.ring_off, st), "ring offsets");
+  CG_HIP(cg::launch_permute(g->sorted_vals, w.ring_off + 4 * nside, n, w.rec, data, dtype, ld,
+                            g->nchan, with_data, npack, n, w.sx, w.sdata, st),
          "permute");
-  const uint64_t* range_off = g->range_off.as<uint64_t>();
-  const uint32_t* ranges = g->ranges.as<uint32_t>();
+  g->last_n = n;
+  g->have_ranges = false;
   if (g->lookup == CG_LOOKUP_DISK) {
     s = run_disk_lookup(g, n, st);
     if (s != CG_OK) return s;
-    range_off = g->dk_range_off.as<uint64_t>();
-    ranges = g->dk_ranges.as<uint32_t>();
   } else {
     CG_HIP(cg::launch_tile_ranges(g->ntiles, g->ring_first.as<int32_t>(),
                                   g->range_off.as<uint64_t>(), g->win.as<uint32_t>(),
-                                  g->sorted_keys, roff, g->ranges.as<uint32_t>(),
+                                  g->sorted_keys, w.ring_off, g->ranges.as<uint32_t>(),
                                   g->nranges.as<uint32_t>(), g->ncand.as<uint64_t>(), st),
            "tile ranges");
   }
-  CG_HIP(cg::scan_u64(g->ncand.as<uint64_t>(), g->cand_off.as<uint64_t>(), g->ntiles, st),
-         "scan candidates");
-  CG_HIP(hipMemcpyAsync(g->h_word, g->cand_off.as<uint64_t>() + g->ntiles, sizeof(uint64_t),
-                        hipMemcpyDeviceToHost, st),
-         "read candidates");
-  CG_HIP(hipStreamSynchronize(st), "sync candidates");
-  const int64_t total = (int64_t)g->h_word[0];
-  g->last_ncand = total;
-  g->last_n = n;
-  const int64_t tc = total > 0 ? total : 1;
-  CG_HIP(ensure(g->cand, sizeof(uint32_t) * tc), "alloc candidates");
-  if (full_records) {
-    CG_HIP(ensure(g->crow, sizeof(uint32_t) * tc), "alloc candidates");
-    CG_HIP(ensure(g->cxyz, sizeof(double) * 3 * tc), "alloc candidates");
-    g->ncap = tc;
-  }
-  CG_HIP(cg::launch_expand(range_off, ranges, g->nranges.as<uint32_t>(), g->cand_off.as<uint64_t>(), g->ntiles,
-                           g->sorted_vals, g->sx.as<double>(), n, g->cand.as<uint32_t>(),
-                           g->crow.as<uint32_t>(), g->cxyz.as<double>(), g->ncap, full_records,
-                           st),
-         "expand");
+  g->have_ranges = true;
   return CG_OK;
 }
 
@@ -202,19 +173,43 @@ cg::TileView tile_view(const cg_gridder* g) {
   cg::TileView tv;
   tv.txyz = g->txyz.as<double>();
   tv.tll = g->tll.as<double>();
-  tv.cand_off = g->cand_off.as<uint64_t>();
-  tv.cand = g->cand.as<uint32_t>();
-  tv.crow = g->crow.as<uint32_t>();
-  tv.cxyz = g->cxyz.as<double>();
+  const bool disk = g->lookup == CG_LOOKUP_DISK;
+  tv.rng = disk ? g->dk_ranges.as<uint32_t>() : g->ranges.as<uint32_t>();
+  tv.roff = disk ? g->dk_range_off.as<uint64_t>() : g->range_off.as<uint64_t>();
+  tv.nr = g->nranges.as<uint32_t>();
+  tv.ntot = g->ncand.as<uint64_t>();
   tv.nslots = g->nslots;
-  tv.ncap = g->ncap;
   // the sorted samples of the last lookup (unit vectors SoA, stride last_n)
   tv.svals = g->sorted_vals;
-  tv.sx = g->sx.as<double>();
+  tv.sx = g->ws.sx;
   tv.nsorted = g->last_n;
+  tv.row0 = 0;
   tv.ntiles = g->ntiles;
   tv.ntx = g->kind == 0 ? g->ntx : 0;
   return tv;
+}
+
+// Workspace bytes of a grid call on n samples with the handle's settings.
+size_t ws_bytes_for(const cg_gridder* g, int64_t n) {
+  return workspace_layout(n, g->nside, small_c(g) ? g->nchan : 0, nullptr, nullptr);
+}
+
+// The workspace of a grid call: the caller's (checked for size and
+// alignment), or the handle's own, grown through the handle's allocator.
+cg_status call_workspace(cg_gridder* g, int64_t n, void* ws, size_t ws_bytes, hipStream_t st,
+                         char** base) {
+  const size_t need = ws_bytes_for(g, n);
+  if (ws) {
+    if (ws_bytes < need)
+      return fail(CG_E_WORKSPACE, "workspace of %zu bytes, %zu needed (cg_workspace_size)",
+                  ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return fail(CG_E_INVALID, "workspace not 256-byte aligned");
+    *base = (char*)ws;
+    return CG_OK;
+  }
+  CG_HIP(ensure(g->alloc, g->own_ws, need, st), "alloc workspace");
+  *base = g->own_ws.as<char>();
+  return CG_OK;
 }
 
 cg_status check_grid_args(const cg_gridder* g, const double* lon, const double* lat,
@@ -248,8 +243,7 @@ cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
     CG_HIP(hipEventRecord(pe->first, st), "event record");
   }
   if (g->prec == CG_PREC_FP32) {
-    CG_HIP(cg::launch_gather_fp32(tv, g->kp, data, dtype, ld, g->sdata.as<float>(), g->nchan, ov,
-                                  st),
+    CG_HIP(cg::launch_gather_fp32(tv, g->kp, data, dtype, ld, g->ws.sdata, g->nchan, ov, st),
            "gather");
   } else {
     CG_HIP(cg::launch_gather_mfma(tv, g->kp, data, g->zrow.p, dtype, ld, g->nchan, g->prec, ov, st),
@@ -259,12 +253,66 @@ cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
   return CG_OK;
 }
 
+// grid + normalise into the caller's cube (the body of cg_grid_datacube and
+// of its variant on the library's static scratch), with the workspace at base
+cg_status grid_datacube_ws(cg_gridder* g, const double* lon_deg, const double* lat_deg,
+                           const void* data, int32_t dtype, int64_t nsamples, int64_t ld_data,
+                           float* cube_out, float* weights_out, char* base, hipStream_t st) {
+  cg_status s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g), base,
+                           st);
+  if (s != CG_OK) return s;
+  cg::OutView ov{};
+  ov.cube = cube_out;
+  ov.wout = weights_out;
+  cube_strides(g, &ov.cst, &ov.tst);
+  ov.slot_target = g->slot_target.as<int32_t>();
+  ov.ntarget = g->ntarget;
+  ov.mode = cg::ACC_FINAL;
+  return contract(g, data, dtype, ld_data, ov, st);
+}
+
+cg_status empty_datacube(cg_gridder* g, float* cube_out, float* weights_out, hipStream_t st) {
+  CG_HIP(cg::launch_fill(cube_out, g->nchan * g->ntarget, __builtin_nanf(""), st), "fill");
+  if (weights_out) CG_HIP(cg::launch_fill(weights_out, g->ntarget, 0.0f, st), "fill");
+  return CG_OK;
+}
+
+void destroy_buffers(cg_gridder* g) {
+  DevBuf* bufs[] = {&g->txyz, &g->tll, &g->slot_target, &g->target_slot, &g->caps,
+                    &g->ring_first, &g->span_bound, &g->range_off, &g->win, &g->ranges,
+                    &g->nranges, &g->ncand, &g->S, &g->W, &g->Wn, &g->flag, &g->zrow, &g->ktab,
+                    &g->own_ws, &g->dk_tkeys, &g->dk_tvals, &g->dk_tkeys2, &g->dk_tvals2,
+                    &g->dk_thist, &g->dk_troff, &g->dk_tab, &g->dk_flag, &g->dk_uoff,
+                    &g->dk_upix, &g->dk_ustart, &g->dk_cnt, &g->dk_off, &g->dk_pk, &g->dk_pv,
+                    &g->dk_pk2, &g->dk_pv2, &g->dk_phist, &g->dk_rsx, &g->dk_ranges,
+                    &g->dk_range_off, &g->dk_scan};
+  for (DevBuf* b : bufs) b->release();
+}
+
+cg_gridder* new_gridder() {
+  cg_gridder* g = new cg_gridder();
+  (void)hipGetDevice(&g->device);
+  g->alloc = current_allocator(g->device);
+  return g;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* cg_last_error(void) { return g_err.c_str(); }
-const char* cg_version(void) { return "cg 0.1 (gfx950)"; }
+const char* cg_version(void) { return "cg 0.2 (gfx950)"; }
+
+cg_status cg_set_allocator(cg_alloc_fn alloc_fn, cg_free_fn free_fn, void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return fail(CG_E_INVALID, "give both an allocation and a free function, or neither");
+  GlobalAllocator& a = global_allocator();
+  std::lock_guard<std::mutex> lk(a.mu);
+  a.fa = alloc_fn;
+  a.ff = free_fn;
+  a.ctx = alloc_fn ? ctx : nullptr;
+  return CG_OK;
+}
 
 cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan) {
   if (!out || !wcs) return fail(CG_E_INVALID, "null pointer");
@@ -282,8 +330,7 @@ cg_status cg_create_wcs(cg_gridder** out, const cg_wcs* wcs, int64_t nchan) {
   if (fabs(wcs->crval2) > 90.0) return fail(CG_E_INVALID, "|CRVAL2| > 90");
   const int64_t nt = wcs->naxis1 * wcs->naxis2;
   if (nt >= (1ll << 31) - 64) return fail(CG_E_UNSUPPORTED, "grid too large");
-  cg_gridder* g = new cg_gridder();
-  (void)hipGetDevice(&g->device);
+  cg_gridder* g = new_gridder();
   g->kind = 0;
   g->wcs.proj = wcs->proj;
   g->wcs.naxis1 = wcs->naxis1;
@@ -330,8 +377,7 @@ cg_status cg_create_sightlines(cg_gridder** out, const double* lon_deg, const do
   if (nchan < 1 || nchan > 65535) return fail(CG_E_INVALID, "nchan must be in [1, 65535]");
   if (ntarget >= (1ll << 31) - 64) return fail(CG_E_UNSUPPORTED, "too many targets");
   hipStream_t st = (hipStream_t)stream;
-  cg_gridder* g = new cg_gridder();
-  (void)hipGetDevice(&g->device);
+  cg_gridder* g = new_gridder();
   g->kind = 1;
   g->ntarget = ntarget;
   g->nchan = nchan;
@@ -340,11 +386,12 @@ cg_status cg_create_sightlines(cg_gridder** out, const double* lon_deg, const do
   cg_status s = alloc_targets(g);
   DevBuf k1, v1, k2, v2, h;
   if (s == CG_OK) {
-    hipError_t e = ensure(k1, 4 * ntarget);
-    if (e == hipSuccess) e = ensure(v1, 4 * ntarget);
-    if (e == hipSuccess) e = ensure(k2, 4 * ntarget);
-    if (e == hipSuccess) e = ensure(v2, 4 * ntarget);
-    if (e == hipSuccess) e = ensure(h, 4 * cg::radix_hist_elems(ntarget));
+    const Allocator& al = g->alloc;
+    hipError_t e = ensure(al, k1, 4 * ntarget, st);
+    if (e == hipSuccess) e = ensure(al, v1, 4 * ntarget, st);
+    if (e == hipSuccess) e = ensure(al, k2, 4 * ntarget, st);
+    if (e == hipSuccess) e = ensure(al, v2, 4 * ntarget, st);
+    if (e == hipSuccess) e = ensure(al, h, 4 * cg::radix_hist_elems(ntarget), st);
     if (e == hipSuccess)
       e = cg::launch_sl_keys(lon_deg, lat_deg, ntarget, k1.as<uint32_t>(), v1.as<uint32_t>(),
                              g->flag.as<int>(), st);
@@ -383,8 +430,7 @@ cg_status cg_create_healpix(cg_gridder** out, int64_t nside, int32_t order, int6
   if (nchan < 1 || nchan > 65535) return fail(CG_E_INVALID, "nchan must be in [1, 65535]");
   hipStream_t st = (hipStream_t)stream;
   const int64_t ntarget = cg::hpx::npix(nside);
-  cg_gridder* g = new cg_gridder();
-  (void)hipGetDevice(&g->device);
+  cg_gridder* g = new_gridder();
   g->kind = 1;
   g->ntarget = ntarget;
   g->nchan = nchan;
@@ -393,9 +439,10 @@ cg_status cg_create_healpix(cg_gridder** out, int64_t nside, int32_t order, int6
   cg_status s = alloc_targets(g);
   DevBuf lon, lat, ord;
   if (s == CG_OK) {
-    hipError_t e = ensure(lon, sizeof(double) * ntarget);
-    if (e == hipSuccess) e = ensure(lat, sizeof(double) * ntarget);
-    if (e == hipSuccess) e = ensure(ord, sizeof(uint32_t) * ntarget);
+    const Allocator& al = g->alloc;
+    hipError_t e = ensure(al, lon, sizeof(double) * ntarget, st);
+    if (e == hipSuccess) e = ensure(al, lat, sizeof(double) * ntarget, st);
+    if (e == hipSuccess) e = ensure(al, ord, sizeof(uint32_t) * ntarget, st);
     if (e == hipSuccess)
       e = cg::launch_hpx_centres(nside, order == CG_HPX_NESTED, lon.as<double>(), lat.as<double>(),
                                  ord.as<uint32_t>(), st);
@@ -432,10 +479,13 @@ cg_status cg_hpx_centres(int64_t nside, int32_t order, int64_t first, int64_t co
   return CG_OK;
 }
 
+
 cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params, int32_t nparams,
                         double support_deg, double hpx_maxres_deg) {
   if (!g) return fail(CG_E_INVALID, "null handle");
   if (!params) return fail(CG_E_INVALID, "null params");
+  // every argument is checked before the handle changes, so a rejected call
+  // leaves the previous kernel (and its table) in force
   cg::KernelParams kp{};
   if (kernel_type == CG_GAUSS1D) {
     if (nparams != 1) return fail(CG_E_INVALID, "gauss1d takes 1 parameter (sigma)");
@@ -469,17 +519,7 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
     if (!(dmax > 0.0) || !isfinite(dmax)) return fail(CG_E_INVALID, "dmax must be > 0");
     for (int32_t k = 1; k < nparams; ++k)
       if (!isfinite(params[k])) return fail(CG_E_INVALID, "table values must be finite");
-    {
-      const cg_status sd = set_dev(g);
-      if (sd != CG_OK) return sd;
-    }
-    // earlier grid calls may still read the previous table
-    CG_HIP(hipDeviceSynchronize(), "sync before the kernel table changes");
-    CG_HIP(ensure(g->ktab, sizeof(double) * (nparams - 1)), "alloc kernel table");
-    CG_HIP(hipMemcpy(g->ktab.p, params + 1, sizeof(double) * (nparams - 1), hipMemcpyHostToDevice),
-           "upload kernel table");
     kp.type = 3;
-    kp.tab = g->ktab.as<double>();
     kp.ntab = nparams - 1;
     kp.tinv = (double)(nparams - 2) / dmax;
   } else {
@@ -498,20 +538,43 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
     nside = 1;
     while (nside < 8192 && sqrt(cg::hpx::kPi / 3.0) / (double)nside > res) nside *= 2;
   }
+  if (kp.type == 3) {
+    const cg_status sd = set_dev(g);
+    if (sd != CG_OK) return sd;
+    // the new table goes into a buffer of its own; the old one stays in
+    // force (earlier grid calls may still read it) until the upload worked
+    DevBuf tab;
+    const size_t bytes = sizeof(double) * (size_t)kp.ntab;
+    hipError_t e = g->alloc.get(tab, bytes);
+    if (e == hipSuccess) e = hipMemcpy(tab.p, params + 1, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();   // earlier grid calls are done with the old table
+    if (e != hipSuccess) {
+      tab.release();
+      return hip_fail(e, "kernel table");
+    }
+    g->ktab.release();
+    g->ktab = tab;
+    kp.tab = g->ktab.as<double>();
+  }
   g->kp = kp;
   g->support_rad = rs;
   g->nside = nside;
   g->kernel_set = true;
   g->span_valid = false;
   g->disk_valid = false;
-  return CG_OK;
+  // the lookup tables of the targets for this support and nside
+  const cg_status sd = set_dev(g);
+  if (sd != CG_OK) return sd;
+  return ensure_span(g, nullptr);
 }
+
 
 cg_status cg_set_lookup(cg_gridder* g, int32_t lookup) {
   if (!g) return fail(CG_E_INVALID, "null handle");
   if (lookup != CG_LOOKUP_TILES && lookup != CG_LOOKUP_DISK)
     return fail(CG_E_INVALID, "unknown lookup %d", lookup);
   g->lookup = lookup;
+  g->have_ranges = false;
   return CG_OK;
 }
 
@@ -530,7 +593,10 @@ cg_status cg_set_nside(cg_gridder* g, int64_t nside) {
   g->nside_fixed = true;
   g->span_valid = false;
   g->disk_valid = false;
-  return CG_OK;
+  if (!g->kernel_set) return CG_OK;
+  const cg_status s = set_dev(g);
+  if (s != CG_OK) return s;
+  return ensure_span(g, nullptr);
 }
 
 cg_status cg_set_output_layout(cg_gridder* g, int32_t layout) {
@@ -550,18 +616,28 @@ cg_status cg_set_precision(cg_gridder* g, int32_t prec) {
   return CG_OK;
 }
 
+cg_status cg_workspace_size(const cg_gridder* g, int64_t nsamples, size_t* bytes) {
+  if (!g || !bytes) return fail(CG_E_INVALID, "null pointer");
+  if (!g->kernel_set) return fail(CG_E_STATE, "set_kernel must be called first");
+  if (nsamples < 0 || nsamples > 0xFFFFFFFFll - 1) return fail(CG_E_INVALID, "bad nsamples");
+  *bytes = ws_bytes_for(g, nsamples);
+  return CG_OK;
+}
+
 cg_status cg_grid(cg_gridder* g, const double* lon_deg, const double* lat_deg, const void* data,
-                  int32_t dtype, int64_t nsamples, int64_t ld_data, void* stream) {
+                  int32_t dtype, int64_t nsamples, int64_t ld_data, void* ws, size_t ws_bytes,
+                  void* stream) {
   cg_status s = check_grid_args(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data);
   if (s != CG_OK || nsamples == 0) return s;
   if ((s = set_dev(g)) != CG_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  CG_HIP(ensure(g->S, sizeof(float) * g->nchan * g->nslots), "alloc accumulators");
-  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g),
-                 g->prec != CG_PREC_FP32, st);
+  char* base = nullptr;
+  if ((s = call_workspace(g, nsamples, ws, ws_bytes, st, &base)) != CG_OK) return s;
+  CG_HIP(ensure(g->alloc, g->S, sizeof(double) * g->nchan * g->nslots, st), "alloc accumulators");
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g), base, st);
   if (s != CG_OK) return s;
   cg::OutView ov{};
-  ov.S = g->S.as<float>();
+  ov.S = g->S.as<double>();
   ov.W = g->W.as<double>();
   ov.Wn = g->Wn.as<double>();
   ov.slot_target = g->slot_target.as<int32_t>();
@@ -574,29 +650,19 @@ cg_status cg_grid(cg_gridder* g, const double* lon_deg, const double* lat_deg, c
 
 cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* lat_deg,
                            const void* data, int32_t dtype, int64_t nsamples, int64_t ld_data,
-                           float* cube_out, float* weights_out, void* stream) {
+                           float* cube_out, float* weights_out, void* ws, size_t ws_bytes,
+                           void* stream) {
   cg_status s = check_grid_args(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data);
   if (s != CG_OK) return s;
   if (!cube_out) return fail(CG_E_INVALID, "null cube_out");
   if ((s = set_dev(g)) != CG_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   g->fresh = true;
-  if (nsamples == 0) {
-    CG_HIP(cg::launch_fill(cube_out, g->nchan * g->ntarget, __builtin_nanf(""), st), "fill");
-    if (weights_out) CG_HIP(cg::launch_fill(weights_out, g->ntarget, 0.0f, st), "fill");
-    return CG_OK;
-  }
-  s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g),
-                 g->prec != CG_PREC_FP32, st);
-  if (s != CG_OK) return s;
-  cg::OutView ov{};
-  ov.cube = cube_out;
-  ov.wout = weights_out;
-  cube_strides(g, &ov.cst, &ov.tst);
-  ov.slot_target = g->slot_target.as<int32_t>();
-  ov.ntarget = g->ntarget;
-  ov.mode = cg::ACC_FINAL;
-  return contract(g, data, dtype, ld_data, ov, st);
+  if (nsamples == 0) return empty_datacube(g, cube_out, weights_out, st);
+  char* base = nullptr;
+  if ((s = call_workspace(g, nsamples, ws, ws_bytes, st, &base)) != CG_OK) return s;
+  return grid_datacube_ws(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data, cube_out,
+                          weights_out, base, st);
 }
 
 cg_status cg_get_datacube(cg_gridder* g, float* out, void* stream) {
@@ -611,7 +677,7 @@ cg_status cg_get_datacube(cg_gridder* g, float* out, void* stream) {
   }
   int64_t cst, tst;
   cube_strides(g, &cst, &tst);
-  CG_HIP(cg::launch_normalize(g->S.as<float>(), g->W.as<double>(), g->Wn.as<double>(),
+  CG_HIP(cg::launch_normalize(g->S.as<double>(), g->W.as<double>(), g->Wn.as<double>(),
                               g->target_slot.as<int32_t>(), g->nslots, g->nchan, g->ntarget, cst,
                               tst, out, nullptr, st),
          "normalize");
@@ -674,7 +740,10 @@ cg_status cg_neighbour_stats(cg_gridder* g, const double* lon_deg, const double*
     return CG_OK;
   }
   if (!lon_deg || !lat_deg) return fail(CG_E_INVALID, "null coordinate pointer");
-  s = run_lookup(g, lon_deg, lat_deg, nsamples, nullptr, CG_F32, g->nchan, false, false, st);
+  const size_t need = workspace_layout(nsamples, g->nside, 0, nullptr, nullptr);
+  CG_HIP(ensure(g->alloc, g->own_ws, need, st), "alloc workspace");
+  s = run_lookup(g, lon_deg, lat_deg, nsamples, nullptr, CG_F32, g->nchan, false,
+                 g->own_ws.as<char>(), st);
   if (s != CG_OK) return s;
   CG_HIP(cg::launch_stats(tile_view(g), g->kp, g->slot_target.as<int32_t>(), counts, hashes, st),
          "stats");
@@ -688,7 +757,21 @@ cg_status cg_query(const cg_gridder* g, int32_t what, int64_t* value) {
     case 1: *value = g->nchan; break;
     case 2: *value = g->nside; break;
     case 3: *value = g->ntiles; break;
-    case 4: *value = g->last_ncand; break;
+    case 4: {
+      // candidates of the last lookup: waits for the device and sums the
+      // per-tile counts
+      *value = 0;
+      if (!g->have_ranges || g->ntiles <= 0) break;
+      CG_HIP(hipSetDevice(g->device), "hipSetDevice");
+      std::vector<uint64_t> c((size_t)g->ntiles);
+      CG_HIP(hipDeviceSynchronize(), "sync");
+      CG_HIP(hipMemcpy(c.data(), g->ncand.p, sizeof(uint64_t) * c.size(), hipMemcpyDeviceToHost),
+             "read candidates");
+      uint64_t t = 0;
+      for (uint64_t v : c) t += v;
+      *value = (int64_t)t;
+      break;
+    }
     case 5: *value = g->prec; break;
     case 6: *value = g->device; break;
     case 7: *value = g->layout; break;
@@ -727,16 +810,7 @@ void cg_destroy(cg_gridder* g) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
-  DevBuf* bufs[] = {&g->txyz, &g->tll, &g->slot_target, &g->target_slot, &g->caps,
-                    &g->ring_first, &g->span_bound, &g->range_off, &g->win, &g->S, &g->W, &g->Wn, &g->flag, &g->zrow,
-                    &g->keys, &g->vals, &g->keys2, &g->vals2, &g->hist, &g->ring_off, &g->sx,
-                    &g->sdata, &g->ranges, &g->nranges, &g->ncand, &g->cand_off, &g->cand,
-                    &g->crow, &g->cxyz, &g->rec, &g->ktab, &g->dk_tkeys, &g->dk_tvals,
-                    &g->dk_tkeys2, &g->dk_tvals2, &g->dk_thist, &g->dk_troff, &g->dk_tab,
-                    &g->dk_flag, &g->dk_uoff, &g->dk_upix, &g->dk_ustart, &g->dk_cnt,
-                    &g->dk_off, &g->dk_pk, &g->dk_pv, &g->dk_pk2, &g->dk_pv2, &g->dk_phist,
-                    &g->dk_rsx, &g->dk_ranges, &g->dk_range_off, &g->dk_scan};
-  for (DevBuf* b : bufs) b->release();
+  destroy_buffers(g);
   if (g->h_word) (void)hipHostFree(g->h_word);
   delete g;
 }

@@ -9,6 +9,7 @@ using namespace cgh;
 
 struct cg_batch {
   int device = 0;
+  Allocator alloc;   // where the batch's buffers come from (captured at creation)
   int32_t dtype = CG_BF16;
   int32_t prec = CG_PREC_BF16;
   std::vector<cg_gridder*> jobs;
@@ -25,8 +26,7 @@ struct cg_batch {
   int64_t* pin_off = nullptr;                // pinned staging of noff | toff | rooff
   uint64_t* pin_word = nullptr;
   DevBuf d_jobs, d_off, keys, vals, keys2, vals2, hist, ring_off, sx, ranges, nranges, ncand,
-      cand_off, cand, crow, cxyz, zrow, items, counter, flags;
-  int64_t ncap = 0, last_ncand = 0;
+      zrow, items, counter, flags;
   bool sorted_in_tmp = false;               // which key/value buffers hold the sorted run
   // work queue
   std::vector<cg::BatchItem> hitems;
@@ -63,7 +63,7 @@ cg_status grow(cg_batch* b, DevBuf& buf, size_t bytes, const char* what) {
   if (bytes == 0) bytes = 1;
   if (buf.bytes >= bytes) return CG_OK;
   drop_graph(b);
-  CG_HIP(ensure(buf, bytes), what);
+  CG_HIP(ensure(b->alloc, buf, bytes), what);
   return CG_OK;
 }
 
@@ -242,7 +242,6 @@ cg_status lookup_part(cg_batch* b, hipStream_t st) {
   const int njobs = (int)b->jobs.size();
   const cg::BatchJob* dj = b->d_jobs.as<cg::BatchJob>();
   int* flags = b->flags.as<int>();
-  CG_HIP(cg::launch_fill(reinterpret_cast<float*>(flags + 1), 1, 0.0f, st), "clear overflow");
   CG_HIP(cg::launch_batch_prep(dj, dev_noff(b), njobs, b->ntot, b->keys.as<uint32_t>(),
                                b->vals.as<uint32_t>(), flags, st),
          "batch prep");
@@ -265,8 +264,6 @@ cg_status lookup_part(cg_batch* b, hipStream_t st) {
                                       b->ring_off.as<uint32_t>(), b->ranges.as<uint32_t>(),
                                       b->nranges.as<uint32_t>(), b->ncand.as<uint64_t>(), st),
          "batch tile ranges");
-  CG_HIP(cg::scan_u64(b->ncand.as<uint64_t>(), b->cand_off.as<uint64_t>(), b->ntiles, st),
-         "batch scan");
   return CG_OK;
 }
 
@@ -274,19 +271,9 @@ const uint32_t* sorted_vals(const cg_batch* b) {
   return b->sorted_in_tmp ? b->vals2.as<uint32_t>() : b->vals.as<uint32_t>();
 }
 
-// Device work after the scan: guard, expand, contraction.
+// Device work after the lookup: the persistent contraction over the queue.
 cg_status contract_part(cg_batch* b, hipStream_t st, bool events) {
-  const int njobs = (int)b->jobs.size();
   const cg::BatchJob* dj = b->d_jobs.as<cg::BatchJob>();
-  int* flags = b->flags.as<int>();
-  CG_HIP(cg::launch_batch_guard(b->cand_off.as<uint64_t>(), b->ntiles, b->ncap, flags + 1, st),
-         "batch guard");
-  CG_HIP(cg::launch_batch_expand(dj, dev_toff(b), njobs, b->ntiles, b->ranges.as<uint32_t>(),
-                                 b->nranges.as<uint32_t>(), b->cand_off.as<uint64_t>(),
-                                 sorted_vals(b), b->sx.as<double>(), b->ntot,
-                                 b->cand.as<uint32_t>(), b->crow.as<uint32_t>(),
-                                 b->cxyz.as<double>(), b->ncap, flags + 1, st),
-         "batch expand");
   CG_HIP(cg::launch_fill(b->counter.as<float>(), 1, 0.0f, st), "clear counter");
   std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
   if (events) {
@@ -294,10 +281,15 @@ cg_status contract_part(cg_batch* b, hipStream_t st, bool events) {
     if (s != CG_OK) return s;
     if (pe) CG_HIP(hipEventRecord(pe->first, st), "event record");
   }
+  cg::BatchRanges br;
+  br.ranges = b->ranges.as<uint32_t>();
+  br.nranges = b->nranges.as<uint32_t>();
+  br.ncand = b->ncand.as<uint64_t>();
+  br.svals = sorted_vals(b);
+  br.sx = b->sx.as<double>();
+  br.nsorted = b->ntot;
   CG_HIP(cg::launch_batch_mfma(dj, b->items.as<cg::BatchItem>(), b->nitems, b->counter.as<int>(),
-                               b->cand_off.as<uint64_t>(), b->cand.as<uint32_t>(),
-                               b->crow.as<uint32_t>(), b->cxyz.as<double>(), b->ncap, b->zrow.p,
-                               b->dtype, b->prec, b->shape, b->bpc, flags + 1, st),
+                               br, b->zrow.p, b->dtype, b->prec, b->shape, b->bpc, st),
          "batch contraction");
   if (pe) CG_HIP(hipEventRecord(pe->second, st), "event record");
   return CG_OK;
@@ -325,33 +317,15 @@ bool need_items(const cg_batch* b, const cg_batch_job* in) {
   return false;
 }
 
-// One eager pass: tables, lookup, one synchronisation to size the candidate
-// lists, then expansion and contraction.
+// One eager pass: tables, lookup and contraction.  Every buffer is sized
+// from the sample counts (known on the host), so the pass does not wait for
+// the device except to reuse the pinned staging buffers of the tables.
 cg_status eager_pass(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
   cg_status s = upload_tables(b, in, st);
   if (s != CG_OK) return s;
   if ((s = size_pass(b)) != CG_OK) return s;
   if (need_items(b, in) && (s = build_items(b, in, st)) != CG_OK) return s;
   if ((s = lookup_part(b, st)) != CG_OK) return s;
-  CG_HIP(hipMemcpyAsync(b->pin_word, b->cand_off.as<uint64_t>() + b->ntiles, sizeof(uint64_t),
-                        hipMemcpyDeviceToHost, st),
-         "read candidates");
-  CG_HIP(hipStreamSynchronize(st), "sync candidates");
-  const int64_t total = (int64_t)b->pin_word[0];
-  b->last_ncand = total;
-  const int64_t tc = std::max<int64_t>(total, 1);
-  if (tc > b->ncap) {
-    // the candidate stride is part of every launch: reallocate all three
-    drop_graph(b);
-    b->cand.release();
-    b->crow.release();
-    b->cxyz.release();
-    const int64_t cap = tc + tc / 8;
-    CG_HIP(ensure(b->cand, 4 * cap), "alloc candidates");
-    CG_HIP(ensure(b->crow, 4 * cap), "alloc candidates");
-    CG_HIP(ensure(b->cxyz, 24 * cap), "alloc candidates");
-    b->ncap = cap;
-  }
   return contract_part(b, st, true);
 }
 
@@ -379,6 +353,7 @@ cg_status cg_batch_create(cg_batch** out, cg_gridder* const* jobs, int32_t njobs
   }
   cg_batch* b = new cg_batch();
   b->device = jobs[0]->device;
+  b->alloc = current_allocator(b->device);
   b->dtype = dtype;
   b->prec = jobs[0]->prec;
   b->jobs.assign(jobs, jobs + njobs);
@@ -410,15 +385,15 @@ cg_status cg_batch_create(cg_batch** out, cg_gridder* const* jobs, int32_t njobs
   b->bits = bits_for((uint64_t)cg::hpx::npix(maxside));
   if (b->ntiles >= (1ll << 31)) return done(fail(CG_E_UNSUPPORTED, "too many tiles"));
   const int64_t nt = std::max<int64_t>(b->ntiles, 1);
-  if ((e = ensure(b->d_jobs, sizeof(cg::BatchJob) * njobs)) != hipSuccess ||
-      (e = ensure(b->d_off, sizeof(int64_t) * 3 * (njobs + 1))) != hipSuccess ||
-      (e = ensure(b->ring_off, 4 * std::max<int64_t>(b->nro, 1))) != hipSuccess ||
-      (e = ensure(b->ranges, 8 * std::max<int64_t>(b->nranges_tot, 1))) != hipSuccess ||
-      (e = ensure(b->nranges, 4 * nt)) != hipSuccess ||
-      (e = ensure(b->ncand, 8 * nt)) != hipSuccess ||
-      (e = ensure(b->cand_off, 8 * (nt + 1))) != hipSuccess ||
-      (e = ensure(b->zrow, 8 * 512)) != hipSuccess ||
-      (e = ensure(b->counter, 64)) != hipSuccess || (e = ensure(b->flags, 64)) != hipSuccess)
+  const Allocator& al = b->alloc;
+  if ((e = ensure(al, b->d_jobs, sizeof(cg::BatchJob) * njobs)) != hipSuccess ||
+      (e = ensure(al, b->d_off, sizeof(int64_t) * 3 * (njobs + 1))) != hipSuccess ||
+      (e = ensure(al, b->ring_off, 4 * std::max<int64_t>(b->nro, 1))) != hipSuccess ||
+      (e = ensure(al, b->ranges, 8 * std::max<int64_t>(b->nranges_tot, 1))) != hipSuccess ||
+      (e = ensure(al, b->nranges, 4 * nt)) != hipSuccess ||
+      (e = ensure(al, b->ncand, 8 * nt)) != hipSuccess ||
+      (e = ensure(al, b->zrow, 8 * 512)) != hipSuccess ||
+      (e = ensure(al, b->counter, 64)) != hipSuccess || (e = ensure(al, b->flags, 64)) != hipSuccess)
     return done(hip_fail(e, "alloc batch"));
   if ((e = hipMemset(b->zrow.p, 0, 8 * 512)) != hipSuccess ||
       (e = hipMemset(b->flags.p, 0, 64)) != hipSuccess)
@@ -562,11 +537,10 @@ cg_status cg_batch_sync(cg_batch* b, void* stream) {
   if (!b) return fail(CG_E_INVALID, "null batch");
   CG_HIP(hipSetDevice(b->device), "hipSetDevice");
   CG_HIP(hipStreamSynchronize((hipStream_t)stream), "sync");
-  int f[3] = {0, 0, 0};
-  CG_HIP(hipMemcpy(f, b->flags.p, sizeof f, hipMemcpyDeviceToHost), "read flags");
-  if (f[0] || f[2]) {
+  int f = 0;
+  CG_HIP(hipMemcpy(&f, b->flags.p, sizeof f, hipMemcpyDeviceToHost), "read flags");
+  if (f) {
     CG_HIP(hipMemset(b->flags.p, 0, sizeof f), "clear flags");
-    if (f[2]) return fail(CG_E_STATE, "a replay needed more candidates than captured (capture again)");
     return fail(CG_E_INPUT, "input contained non-finite coordinates or |lat| > 90 (skipped)");
   }
   return CG_OK;
@@ -579,7 +553,20 @@ cg_status cg_batch_query(const cg_batch* b, int32_t what, int64_t* value) {
     case 1: *value = b->ntot; break;
     case 2: *value = b->ntiles; break;
     case 3: *value = b->nitems; break;
-    case 4: *value = b->last_ncand; break;
+    case 4: {
+      // candidates of the last pass: waits for the device, sums the tile counts
+      *value = 0;
+      if (b->ntiles <= 0 || b->ntot <= 0) break;
+      CG_HIP(hipSetDevice(b->device), "hipSetDevice");
+      std::vector<uint64_t> c((size_t)b->ntiles);
+      CG_HIP(hipDeviceSynchronize(), "sync");
+      CG_HIP(hipMemcpy(c.data(), b->ncand.p, sizeof(uint64_t) * c.size(), hipMemcpyDeviceToHost),
+             "read candidates");
+      uint64_t t = 0;
+      for (uint64_t v : c) t += v;
+      *value = (int64_t)t;
+      break;
+    }
     case 5: *value = cg::batch_shape_rows(b->shape); break;
     case 6: *value = b->split; break;
     case 7: *value = b->bpc > 0 ? b->bpc : cg::batch_max_blocks_per_cu(b->dtype, b->prec, b->shape); break;
@@ -622,8 +609,8 @@ void cg_batch_destroy(cg_batch* b) {
     (void)hipEventDestroy(e.second);
   }
   DevBuf* bufs[] = {&b->d_jobs, &b->d_off, &b->keys, &b->vals, &b->keys2, &b->vals2, &b->hist,
-                    &b->ring_off, &b->sx, &b->ranges, &b->nranges, &b->ncand, &b->cand_off,
-                    &b->cand, &b->crow, &b->cxyz, &b->zrow, &b->items, &b->counter, &b->flags};
+                    &b->ring_off, &b->sx, &b->ranges, &b->nranges, &b->ncand, &b->zrow,
+                    &b->items, &b->counter, &b->flags};
   for (DevBuf* d : bufs) d->release();
   if (b->pin_jobs) (void)hipHostFree(b->pin_jobs);
   if (b->pin_off) (void)hipHostFree(b->pin_off);

@@ -12,11 +12,6 @@
 
 namespace cg {
 
-__device__ __noinline__ double chord2_to_d2_exact(double c2) {
-  const double d = 2.0 * asin(0.5 * sqrt(c2));
-  return d * d;
-}
-
 // Launch shapes of the persistent kernel (chosen by the autotuner):
 // wavefronts per workgroup and 32-channel blocks per wavefront.
 //   shape 0: 8 x 1 (256 channels per item)    shape 1: 8 x 2 (512)
@@ -26,11 +21,8 @@ __device__ __noinline__ double chord2_to_d2_exact(double c2) {
 template <int NW, int BPW, int MODE, typename T>
 __global__ void __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) k_batch_mfma(
     const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, int64_t nitems,
-    int* counter, const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ cand,
-    const uint32_t* __restrict__ crow, const double* __restrict__ cxyz, int64_t ncap,
-    const T* __restrict__ zrow, const int* __restrict__ ovf) {
+    int* counter, BatchRanges br, const T* __restrict__ zrow) {
   __shared__ int s_item;
-  if (*ovf) return;   // candidate buffers too small: nothing is written
   for (;;) {
     __syncthreads();  // the previous item is done with LDS
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -42,14 +34,17 @@ __global__ void __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) k_batch_mfma(
     TileView tv;
     tv.txyz = jb.txyz;
     tv.tll = jb.tll;
-    tv.cand_off = cand_off + jb.toff;
-    tv.cand = cand;
-    tv.crow = crow;
-    tv.cxyz = cxyz;
+    tv.rng = br.ranges + 2 * jb.rbase;
+    tv.roff = jb.range_off;
+    tv.nr = br.nranges + jb.toff;
+    tv.ntot = br.ncand + jb.toff;
     tv.nslots = jb.nslots;
-    tv.ncap = ncap;
     tv.ntiles = jb.ntiles;
     tv.ntx = jb.ntx;   // same candidate order as the per-grid kernel
+    tv.svals = br.svals;
+    tv.sx = br.sx;
+    tv.nsorted = br.nsorted;
+    tv.row0 = jb.noff;
     OutView ov;
     ov.S = nullptr;
     ov.W = nullptr;
@@ -77,9 +72,8 @@ static int occ_of() {
 
 template <int NW, int BPW, int MODE, typename T>
 static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
-                            int* counter, const uint64_t* cand_off, const uint32_t* cand,
-                            const uint32_t* crow, const double* cxyz, int64_t ncap,
-                            const void* zrow, int blocks_per_cu, const int* ovf, hipStream_t st) {
+                            int* counter, const BatchRanges& br, const void* zrow,
+                            int blocks_per_cu, hipStream_t st) {
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -91,20 +85,16 @@ static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, int64_
   if (grid > nitems) grid = nitems;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((k_batch_mfma<NW, BPW, MODE, T>), dim3((unsigned)grid), dim3(NW * 64), 0, st,
-                     jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap,
-                     (const T*)zrow, ovf);
+                     jobs, items, nitems, counter, br, (const T*)zrow);
   return hipGetLastError();
 }
 
 template <int MODE, typename T>
 static hipError_t launch_bs(int shape, const BatchJob* jobs, const BatchItem* items,
-                            int64_t nitems, int* counter, const uint64_t* cand_off,
-                            const uint32_t* cand, const uint32_t* crow, const double* cxyz,
-                            int64_t ncap, const void* zrow, int blocks_per_cu, const int* ovf,
-                            hipStream_t st) {
-#define CG_BT(NW_, BPW_)                                                                     \
-  launch_bt<NW_, BPW_, MODE, T>(jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap, \
-                                zrow, blocks_per_cu, ovf, st)
+                            int64_t nitems, int* counter, const BatchRanges& br,
+                            const void* zrow, int blocks_per_cu, hipStream_t st) {
+#define CG_BT(NW_, BPW_) \
+  launch_bt<NW_, BPW_, MODE, T>(jobs, items, nitems, counter, br, zrow, blocks_per_cu, st)
   switch (shape) {
     case 0: return CG_BT(8, 1);
     case 1: return CG_BT(8, 2);
@@ -117,13 +107,10 @@ static hipError_t launch_bs(int shape, const BatchJob* jobs, const BatchItem* it
 
 template <int MODE>
 static hipError_t launch_bm(int dtype, int shape, const BatchJob* jobs, const BatchItem* items,
-                            int64_t nitems, int* counter, const uint64_t* cand_off,
-                            const uint32_t* cand, const uint32_t* crow, const double* cxyz,
-                            int64_t ncap, const void* zrow, int blocks_per_cu, const int* ovf,
-                            hipStream_t st) {
-#define CG_BS(T_)                                                                                \
-  launch_bs<MODE, T_>(shape, jobs, items, nitems, counter, cand_off, cand, crow, cxyz, ncap, zrow, \
-                      blocks_per_cu, ovf, st)
+                            int64_t nitems, int* counter, const BatchRanges& br,
+                            const void* zrow, int blocks_per_cu, hipStream_t st) {
+#define CG_BS(T_) \
+  launch_bs<MODE, T_>(shape, jobs, items, nitems, counter, br, zrow, blocks_per_cu, st)
   switch (dtype) {
     case 0: return CG_BS(double);
     case 1: return CG_BS(float);
@@ -134,16 +121,12 @@ static hipError_t launch_bm(int dtype, int shape, const BatchJob* jobs, const Ba
 }
 
 hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
-                             int* counter, const uint64_t* cand_off, const uint32_t* cand,
-                             const uint32_t* crow, const double* cxyz, int64_t ncap,
-                             const void* zrow, int dtype, int prec, int shape, int blocks_per_cu,
-                             const int* ovf, hipStream_t st) {
+                             int* counter, const BatchRanges& br, const void* zrow, int dtype,
+                             int prec, int shape, int blocks_per_cu, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (prec == 2)
-    return launch_bm<1>(dtype, shape, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
-                        ncap, zrow, blocks_per_cu, ovf, st);
-  return launch_bm<0>(dtype, shape, jobs, items, nitems, counter, cand_off, cand, crow, cxyz,
-                      ncap, zrow, blocks_per_cu, ovf, st);
+    return launch_bm<1>(dtype, shape, jobs, items, nitems, counter, br, zrow, blocks_per_cu, st);
+  return launch_bm<0>(dtype, shape, jobs, items, nitems, counter, br, zrow, blocks_per_cu, st);
 }
 
 template <int MODE, typename T>

@@ -193,8 +193,9 @@ __global__ void __launch_bounds__(256) k_range_write(const uint32_t* __restrict_
 }
 
 // One wavefront per tile: its pairs [p0, p1) by binary search over the
-// sorted tiles, its ranges [rsx[p0], rsx[p1]); ends become lengths and sum
-// to the tile's candidate count.
+// sorted tiles, its ranges [rsx[p0], rsx[p1]); each range's end becomes its
+// first candidate index within the tile (the exclusive prefix of the
+// lengths), and the lengths sum to the tile's candidate count.
 __global__ void __launch_bounds__(64) k_tile_disk_ranges(
     const uint32_t* __restrict__ pk, int64_t np, const uint64_t* __restrict__ rsx,
     int64_t ntiles, uint32_t* __restrict__ ranges, uint64_t* __restrict__ range_off,
@@ -204,14 +205,19 @@ __global__ void __launch_bounds__(64) k_tile_disk_ranges(
   const uint32_t p0 = lower_bound_keys(pk, 0, (uint32_t)np, (uint64_t)tile);
   const uint32_t p1 = lower_bound_keys(pk, p0, (uint32_t)np, (uint64_t)tile + 1);
   const uint64_t r0 = rsx[p0], r1 = rsx[p1];
-  double sum = 0.0;
-  for (uint64_t q = r0 + lane; q < r1; q += 64) {
-    const uint32_t len = ranges[2 * q + 1] - ranges[2 * q];
-    ranges[2 * q + 1] = len;
-    sum += (double)len;
-  }
+  uint32_t sum = 0;
+  for (uint64_t q0 = r0; q0 < r1; q0 += 64) {
+    const uint64_t q = q0 + lane;
+    const uint32_t len = q < r1 ? ranges[2 * q + 1] - ranges[2 * q] : 0u;
+    uint32_t incl = len;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    if (q < r1) ranges[2 * q + 1] = sum + (incl - len);
+    sum += (uint32_t)__shfl((int)incl, 63, 64);
+  }
   if (lane == 0) {
     range_off[tile] = r0;
     nranges[tile] = (uint32_t)(r1 - r0);

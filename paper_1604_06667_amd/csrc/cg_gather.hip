@@ -4,16 +4,12 @@
 // W_t += w over the tile's candidate samples n with d <= r_s.  Each tile's
 // outputs are owned by one workgroup, so no atomics are needed (the
 // ownership argument of Sect. 2.2).  The support test is FP64 on unit
-// vectors; weights are FP32; each candidate chunk is summed in FP32 and the
-// chunk sums are added into FP64 totals (two-level summation).
+// vectors; weights are FP32; products and sums are FP64 (an FP32 weight
+// times an FP32 value is exact in FP64), so the result does not depend on
+// the order in which candidates arrive, even where the sums cancel.
 #include "cg_internal.hpp"
 
 namespace cg {
-
-__device__ __noinline__ double chord2_to_d2_exact(double c2) {
-  const double d = 2.0 * asin(0.5 * sqrt(c2));
-  return d * d;
-}
 
 constexpr int kChunk = 64;   // candidates staged per step
 
@@ -60,7 +56,7 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   const int lane = threadIdx.x;
   const int64_t slot = tile * kTile + lane;
   __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
-  __shared__ float s_d[kChunk * CMAX];
+  __shared__ double s_d[kChunk * CMAX];
   const int64_t ns = tv.nslots;
   const double tx = tv.txyz[slot], ty = tv.txyz[ns + slot], tz = tv.txyz[2 * ns + slot];
   double ax[3] = {0.0, 0.0, 0.0}, bx[3] = {0.0, 0.0, 0.0};
@@ -69,19 +65,22 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
 #pragma unroll
   for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
   double wacc = 0.0;
-  const uint64_t c0 = tv.cand_off[tile], c1 = tv.cand_off[tile + 1];
+  const uint32_t total = (uint32_t)tv.ntot[tile];
+  RangeWindow<false> rw;
+  rw.init(tv.rng + 2 * tv.roff[tile], tv.nr[tile], total, true);
   const int64_t cap = tv.nsorted;
   const double thr = 1.0 - 0.5 * kp.cs2 - 2e-15;
-  for (uint64_t base = c0; base < c1; base += kChunk) {
-    const int kmax = (int)((c1 - base) < (uint64_t)kChunk ? (c1 - base) : (uint64_t)kChunk);
+  for (uint32_t base = 0; base < total; base += kChunk) {
+    const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
+    rw.cover(base, base + kmax - 1, true);
+    const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1));
     if (lane < kmax) {
-      const int64_t pos = tv.cand[base + lane];
       s_x[lane] = tv.sx[pos];
       s_y[lane] = tv.sx[cap + pos];
       s_z[lane] = tv.sx[2 * cap + pos];
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
-        if (c < nchan) s_d[lane * CMAX + c] = sdata[pos * nchan + c];
+        if (c < nchan) s_d[lane * CMAX + c] = (double)sdata[pos * nchan + c];
     }
     __syncthreads();
     // candidates of the chunk that may lie within the support of this lane's
@@ -103,26 +102,19 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
         inside = (inside << 1) | (uint64_t)(dot >= thr);
       }
     }
-    float p[CMAX];
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c) p[c] = 0.0f;
-    float pw = 0.0f;
     while (inside) {
       const int k = __builtin_ctzll(inside);
       inside &= inside - 1;
       const double dx = s_x[k] - tx, dy = s_y[k] - ty, dz = s_z[k] - tz;
       const double c2 = dx * dx + dy * dy + dz * dz;
-      const float w = c2 <= kp.cs2 ? pair_weight<RADIAL>(kp, c2, dx, dy, dz, ax[0], ax[1], ax[2], bx[0],
-                                                 bx[1], bx[2])
-                                   : 0.0f;
-      pw += w;
+      const double w = c2 <= kp.cs2 ? (double)pair_weight<RADIAL>(kp, c2, dx, dy, dz, ax[0], ax[1],
+                                                                   ax[2], bx[0], bx[1], bx[2])
+                                    : 0.0;
+      wacc += w;
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
-        if (c < nchan) p[c] = fmaf(w, s_d[k * CMAX + c], p[c]);
+        if (c < nchan) acc[c] = fma(w, s_d[k * CMAX + c], acc[c]);
     }
-    wacc += (double)pw;
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c) acc[c] += (double)p[c];
     __syncthreads();
   }
   if (ov.mode == ACC_FINAL) {
@@ -136,8 +128,8 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   } else {
     const bool add = ov.mode == ACC_ADD;
     for (int c = 0; c < CMAX && c < nchan; ++c) {
-      float* s = ov.S + (int64_t)c * ns + slot;
-      *s = add ? (float)((double)*s + acc[c]) : (float)acc[c];
+      double* s = ov.S + (int64_t)c * ns + slot;
+      *s = add ? *s + acc[c] : acc[c];
     }
     ov.W[slot] = add ? ov.W[slot] + wacc : wacc;
     ov.Wn[slot] = add ? ov.Wn[slot] + wacc : wacc;
@@ -225,15 +217,20 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[i][v] = 0.0;
   }
-  const uint64_t cb0 = tv.cand_off[tile], cb1 = tv.cand_off[tile + 1];
-  for (uint64_t base = cb0; base < cb1; base += kChunk) {
-    const int kmax = (int)((cb1 - base) < (uint64_t)kChunk ? (cb1 - base) : (uint64_t)kChunk);
-    if (t < kmax) {
-      const int64_t pos = tv.cand[base + t];
-      s_x[t] = tv.sx[pos];
-      s_y[t] = tv.sx[cap + pos];
-      s_z[t] = tv.sx[2 * cap + pos];
-      s_row[t] = (int64_t)tv.svals[pos] * ld;
+  const uint32_t total = (uint32_t)tv.ntot[tile];
+  RangeWindow<false> rw;   // used by wavefront 0, which stages the candidates
+  if (wv_id == 0) rw.init(tv.rng + 2 * tv.roff[tile], tv.nr[tile], total, true);
+  for (uint32_t base = 0; base < total; base += kChunk) {
+    const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
+    if (wv_id == 0) {
+      rw.cover(base, base + kmax - 1, true);
+      const int64_t pos = rw.pos(base + (t < kmax ? t : kmax - 1));
+      if (t < kmax) {
+        s_x[t] = tv.sx[pos];
+        s_y[t] = tv.sx[cap + pos];
+        s_z[t] = tv.sx[2 * cap + pos];
+        s_row[t] = (int64_t)tv.svals[pos] * ld;
+      }
     }
     __syncthreads();
     for (int r = wv_id; r < kmax; r += NWV) {
@@ -268,19 +265,14 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
       }
       wl[i] += (double)w;
       uint64_t m = __ballot(w != 0.0f);
-      float p[VEC];
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) p[v] = 0.0f;
       while (m) {
         const int k = __ffsll((unsigned long long)m) - 1;
         m &= m - 1;
-        const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w), k));
+        const double wk = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(w), k));
         const float* dp = &s_d[k * CB + col];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) p[v] = fmaf(wk, dp[v], p[v]);
+        for (int v = 0; v < VEC; ++v) acc[i][v] = fma(wk, (double)dp[v], acc[i][v]);
       }
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) acc[i][v] += (double)p[v];
     }
     __syncthreads();
   }
@@ -291,37 +283,45 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
     if (lane == 0) s_w[wv_id * TPW + i] = s;
   }
   __syncthreads();
-  // transpose the tile's [target][channel] block through LDS: s_d[c][target]
+  // transpose the tile's [target][channel] block through LDS (as FP64, in
+  // two halves of 32 targets): s_dd[c][target]
   const bool fin = ov.mode == ACC_FINAL;
-#pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    const int tt = wv_id * TPW + i;
-    const double wt = s_w[tt];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      float o;
-      if (fin) o = wt > 0.0 ? (float)(acc[i][v] / wt) : qnan_f();
-      else o = (float)acc[i][v];
-      s_d[(col + v) * kTile + tt] = o;
-    }
-  }
-  __syncthreads();
-  // consecutive threads write consecutive targets of a channel, or (target-
-  // major cubes) consecutive channels of a target
   const bool tmaj = fin && ov.tst != 1;
-  for (int idx = t; idx < CB * kTile; idx += 64 * NWV) {
-    const int c = tmaj ? idx % CB : idx / kTile;
-    const int l = tmaj ? idx / CB : idx % kTile;
-    if (c0 + c >= nchan) continue;
-    const int64_t slot = tile * kTile + l;
-    const float o = s_d[c * kTile + l];
-    if (fin) {
-      const int32_t tg = ov.slot_target[slot];
-      if (tg >= 0) ov.cube[(c0 + c) * ov.cst + (int64_t)tg * ov.tst] = o;
-    } else if (ov.mode == ACC_ADD) {
-      ov.S[(c0 + c) * ns + slot] += o;
-    } else {
-      ov.S[(c0 + c) * ns + slot] = o;
+  double* s_dd = reinterpret_cast<double*>(s_d);
+  static_assert(sizeof(s_d) >= sizeof(double) * CB * (kTile / 2), "transpose buffer");
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if (half) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int tt = wv_id * TPW + i;
+      if ((tt >> 5) != half) continue;
+      const double wt = s_w[tt];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        double o;
+        if (fin) o = wt > 0.0 ? acc[i][v] / wt : (double)qnan_f();
+        else o = acc[i][v];
+        s_dd[(col + v) * (kTile / 2) + (tt & 31)] = o;
+      }
+    }
+    __syncthreads();
+    // consecutive threads write consecutive targets of a channel, or (target-
+    // major cubes) consecutive channels of a target
+    for (int idx = t; idx < CB * (kTile / 2); idx += 64 * NWV) {
+      const int c = tmaj ? idx % CB : idx / (kTile / 2);
+      const int l = tmaj ? idx / CB : idx % (kTile / 2);
+      if (c0 + c >= nchan) continue;
+      const int64_t slot = tile * kTile + half * (kTile / 2) + l;
+      const double o = s_dd[c * (kTile / 2) + l];
+      if (fin) {
+        const int32_t tg = ov.slot_target[slot];
+        if (tg >= 0) ov.cube[(c0 + c) * ov.cst + (int64_t)tg * ov.tst] = (float)o;
+      } else if (ov.mode == ACC_ADD) {
+        ov.S[(c0 + c) * ns + slot] += o;
+      } else {
+        ov.S[(c0 + c) * ns + slot] = o;
+      }
     }
   }
   if (pass == 0 && t < kTile) {
@@ -419,11 +419,14 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
   const double tx = tv.txyz[slot], ty = tv.txyz[ns + slot], tz = tv.txyz[2 * ns + slot];
   int32_t cnt = 0;
   uint64_t h = 0;
-  const uint64_t c0 = tv.cand_off[tile], c1 = tv.cand_off[tile + 1];
-  for (uint64_t base = c0; base < c1; base += kChunk) {
-    const int kmax = (int)((c1 - base) < (uint64_t)kChunk ? (c1 - base) : (uint64_t)kChunk);
+  const uint32_t total = (uint32_t)tv.ntot[tile];
+  RangeWindow<false> rw;
+  rw.init(tv.rng + 2 * tv.roff[tile], tv.nr[tile], total, true);
+  for (uint32_t base = 0; base < total; base += kChunk) {
+    const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
+    rw.cover(base, base + kmax - 1, true);
+    const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1));
     if (lane < kmax) {
-      const int64_t pos = tv.cand[base + lane];
       s_x[lane] = tv.sx[pos];
       s_y[lane] = tv.sx[cap + pos];
       s_z[lane] = tv.sx[2 * cap + pos];
@@ -457,7 +460,7 @@ hipError_t launch_stats(const TileView& tv, const KernelParams& kp, const int32_
 // ---------------------------------------------------------------------------
 // Eq. (3): R = S / W (NaN where W = 0) into the caller's layout.
 
-__global__ void __launch_bounds__(256) k_normalize(const float* __restrict__ S,
+__global__ void __launch_bounds__(256) k_normalize(const double* __restrict__ S,
                                                    const double* __restrict__ W,
                                                    const double* __restrict__ Wn,
                                                    const int32_t* __restrict__ target_slot,
@@ -470,12 +473,12 @@ __global__ void __launch_bounds__(256) k_normalize(const float* __restrict__ S,
   const int64_t s = target_slot[t];
   if (cube) {
     const double wn = Wn[s];
-    cube[c * cst + t * tst] = wn > 0.0 ? (float)((double)S[c * nslots + s] / wn) : qnan_f();
+    cube[c * cst + t * tst] = wn > 0.0 ? (float)(S[c * nslots + s] / wn) : qnan_f();
   }
   if (wout && c == 0) wout[t] = (float)W[s];
 }
 
-hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
+hipError_t launch_normalize(const double* S, const double* W, const double* Wn,
                             const int32_t* target_slot, int64_t nslots, int64_t nchan,
                             int64_t ntarget, int64_t cst, int64_t tst, float* cube, float* wout,
                             hipStream_t st) {

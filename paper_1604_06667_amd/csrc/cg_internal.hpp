@@ -29,22 +29,29 @@ struct KernelParams {
   double tinv;       // (ntab - 1) / dmax (per rad)
 };
 
-// Device-side description of one tile's candidate list and target slots.
+// Device-side description of the tiles' candidates and target slots.  The
+// candidates of tile t are the concatenation of its nr[t] ranges of sorted
+// samples: range k (0 <= k < nr[t]) sits at rng[2 (roff[t] + k)] = first
+// sorted position and rng[2 (roff[t] + k) + 1] = its first candidate index
+// within the tile (the exclusive prefix of the range lengths); the tile
+// holds ntot[t] candidates.  Kernels walk the ranges directly (RangeWindow),
+// so no per-candidate list is materialised and nothing about a grid call's
+// memory depends on the data.
 struct TileView {
   const double* txyz;          // [3][nslots] target unit vectors (NaN: no target)
   const double* tll;           // [2][nslots] target lon, lat in radians (gauss2d axes)
-  const uint64_t* cand_off;    // [ntiles + 1] candidate offsets
-  const uint32_t* cand;        // [ncand] sorted-sample position of each candidate
-  const uint32_t* crow;        // [ncand] input index (data row) of each candidate (matrix cores)
-  const double* cxyz;          // [3][ncap] unit vector of each candidate (matrix cores)
+  const uint32_t* rng;         // ranges (first position, first candidate index)
+  const uint64_t* roff;        // [ntiles] offset of each tile's ranges in rng (in ranges)
+  const uint32_t* nr;          // [ntiles] ranges per tile
+  const uint64_t* ntot;        // [ntiles] candidates per tile
   int64_t nslots;
-  int64_t ncap;                // stride of cxyz
   int64_t ntiles;
   int64_t ntx;                 // tiles per row of a WCS grid (0: sight lines)
-  // the sorted samples, read through cand by the FP32 gathers and statistics
-  const uint32_t* svals;       // [nsorted] input index
+  // the sorted samples the ranges point into
+  const uint32_t* svals;       // [nsorted] input index (batches: position in the concatenated input)
   const double* sx;            // [3][nsorted] unit vector
   int64_t nsorted;
+  int64_t row0;                // input index of the first sample of this job (batches), else 0
 };
 
 // Block -> tile map that keeps consecutive tiles on one XCD: workgroups are
@@ -67,6 +74,77 @@ __device__ __forceinline__ void stg(T* p, int64_t i, T v) {
   if constexpr (GL) ((T __attribute__((address_space(1)))*)p)[i] = v;
   else p[i] = v;
 }
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// One wavefront's view of a tile's ranges: lane l holds range w0 + l (its
+// first sorted position b and candidate indices [s, e); past the last range
+// s = e = total).  The 64 ranges cover candidates [s of lane 0, e of lane
+// 63).  cover() moves the window (monotonically, in the direction of the
+// walk) until it holds a span of candidates; pos() then maps a candidate
+// index of that span to its sorted position by a binary search over the
+// lanes.  Every lane of the wavefront must take part in both calls.
+template <bool GL>
+struct RangeWindow {
+  const uint32_t* rng;
+  uint32_t nr, total, w0;
+  uint32_t b, s, e;
+
+  __device__ __forceinline__ void load(uint32_t first) {
+    w0 = first;
+    const uint32_t k = first + (uint32_t)(threadIdx.x & 63);
+    if (k < nr) {
+      b = ldg<GL>(rng, 2 * (int64_t)k);
+      s = ldg<GL>(rng, 2 * (int64_t)k + 1);
+      e = k + 1 < nr ? ldg<GL>(rng, 2 * (int64_t)k + 3) : total;
+    } else {
+      b = 0;
+      s = e = total;
+    }
+  }
+  // tile of `tv`; fwd: the walk visits candidates in increasing order
+  __device__ __forceinline__ void init(const uint32_t* ranges, uint32_t n_ranges, uint32_t n_cand,
+                                       bool fwd) {
+    rng = ranges;
+    nr = n_ranges;
+    total = n_cand;
+    load(fwd || nr <= 64 ? 0u : nr - 64);
+  }
+  // make the window hold candidates [qlo, qhi] (qlo <= qhi < total)
+  __device__ __forceinline__ void cover(uint32_t qlo, uint32_t qhi, bool fwd) {
+    for (;;) {
+      const uint32_t wlo = lane_u32(s, 0), whi = lane_u32(e, 63);
+      if (wlo <= qlo && qhi < whi) return;
+      uint32_t nw;
+      if (fwd) {
+        // the range holding qlo becomes the first of the window: at least 63
+        // more non-empty ranges follow it, which cover any span of 64
+        nw = w0 + (uint32_t)__popcll(__ballot(e <= qlo));
+      } else if (qhi < wlo) {
+        nw = w0 >= 64 ? w0 - 64 : 0;
+      } else {
+        // the range holding qhi becomes the last of the window
+        const uint32_t r = w0 + (uint32_t)__popcll(__ballot(e <= qhi));
+        nw = r >= 63 ? r - 63 : 0;
+      }
+      load(nw);
+    }
+  }
+  // sorted position of candidate q (inside the covered span)
+  __device__ __forceinline__ uint32_t pos(uint32_t q) const {
+    int r = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const uint32_t ev = (uint32_t)__shfl((int)e, r + step - 1, 64);
+      if (ev <= q) r += step;
+    }
+    const uint32_t br = (uint32_t)__shfl((int)b, r, 64);
+    const uint32_t sr = (uint32_t)__shfl((int)s, r, 64);
+    return br + (q - sr);
+  }
+};
+
 __device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t ntiles) {
   const int64_t k = b % kNumXcd;
   const int64_t j = b / kNumXcd;
@@ -105,8 +183,12 @@ __device__ __forceinline__ int64_t strip_tile(int64_t v, int64_t ntiles, int64_t
 // correction c^2 (c^2/12 + ...) is at most 1.1 % of c^2, so it is evaluated
 // in FP32 (its rounding moves d^2 by < 1e-9 relative) and added to c^2 with
 // one FP64 fma: no FP64 constants, which keeps the hot loops' registers
-// free.  Longer chords take the exact form in a separate function.
-__device__ __noinline__ double chord2_to_d2_exact(double c2);
+// free.  Longer chords take the exact form in a separate (not inlined)
+// function.
+__device__ __noinline__ inline double chord2_to_d2_exact(double c2) {
+  const double d = 2.0 * asin(0.5 * sqrt(c2));
+  return d * d;
+}
 __device__ __forceinline__ double chord2_to_d2(double c2) {
   if (c2 <= 0.1225) {
     const float c = (float)c2;
@@ -235,16 +317,10 @@ hipError_t launch_tile_ranges(int64_t ntiles, const int32_t* ring_first,
                               const uint64_t* range_off, const uint32_t* win,
                               const uint32_t* keys, const uint32_t* ring_off, uint32_t* ranges,
                               uint32_t* nranges, uint64_t* ncand, hipStream_t st);
-// full: also the input index and unit vector of every candidate (crow, cxyz)
-hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
-                         const uint64_t* cand_off, int64_t ntiles, const uint32_t* vals,
-                         const double* sx, int64_t nsorted, uint32_t* cand, uint32_t* crow,
-                         double* cxyz, int64_t ncap, bool full, hipStream_t st);
-
 // contraction kernels
 enum AccMode { ACC_OVERWRITE = 0, ACC_ADD = 1, ACC_FINAL = 2 };
 struct OutView {
-  float* S;            // [nchan][nslots] accumulator (ACC_OVERWRITE / ACC_ADD)
+  double* S;           // [nchan][nslots] accumulator (ACC_OVERWRITE / ACC_ADD)
   double* W;           // [nslots] weight map (Eq. 2)
   double* Wn;          // [nslots] normaliser: sum of the weights as they entered the products
   float* cube;         // ACC_FINAL: normalised output in user layout
@@ -326,28 +402,28 @@ hipError_t launch_batch_tile_ranges(const BatchJob* jobs, const int64_t* toff, i
                                     int64_t ntiles, const uint32_t* keys, const uint32_t* ring_off,
                                     uint32_t* ranges, uint32_t* nranges, uint64_t* ncand,
                                     hipStream_t st);
-// ovf[0] = ovf[1] = 1 if the candidates exceed cap (ovf[1] is sticky)
-hipError_t launch_batch_guard(const uint64_t* cand_off, int64_t ntiles, int64_t cap, int* ovf,
-                              hipStream_t st);
-hipError_t launch_batch_expand(const BatchJob* jobs, const int64_t* toff, int njobs, int64_t ntiles,
-                               const uint32_t* ranges, const uint32_t* nranges,
-                               const uint64_t* cand_off, const uint32_t* vals, const double* sx,
-                               int64_t nsorted, uint32_t* cand, uint32_t* crow, double* cxyz,
-                               int64_t ncap, const int* ovf, hipStream_t st);
+// The ranges of a batch lookup pass, over the concatenated jobs: per job at
+// ranges + 2 rbase (job-local range offsets range_off), counts at toff.
+struct BatchRanges {
+  const uint32_t* ranges;
+  const uint32_t* nranges;
+  const uint64_t* ncand;
+  const uint32_t* svals;       // sorted positions in the concatenated input
+  const double* sx;            // [3][nsorted] sorted unit vectors
+  int64_t nsorted;
+};
 // Persistent contraction over a queue of items; shape 0..3 selects the
 // workgroup (8 or 4 wavefronts, 1 or 2 channel blocks each: at most
 // batch_shape_rows(shape) channels per item); counter must be zero at launch.
 constexpr int kBatchShapes = 4;
 hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
-                             int* counter, const uint64_t* cand_off, const uint32_t* cand,
-                             const uint32_t* crow, const double* cxyz, int64_t ncap,
-                             const void* zrow, int dtype, int prec, int shape, int blocks_per_cu,
-                             const int* ovf, hipStream_t st);
+                             int* counter, const BatchRanges& br, const void* zrow, int dtype,
+                             int prec, int shape, int blocks_per_cu, hipStream_t st);
 int batch_max_blocks_per_cu(int dtype, int prec, int shape);
 int batch_shape_rows(int shape);
 hipError_t launch_stats(const TileView& tv, const KernelParams& kp, const int32_t* slot_target,
                         int32_t* counts, uint64_t* hashes, hipStream_t st);
-hipError_t launch_normalize(const float* S, const double* W, const double* Wn,
+hipError_t launch_normalize(const double* S, const double* W, const double* Wn,
                             const int32_t* target_slot, int64_t nslots, int64_t nchan,
                             int64_t ntarget, int64_t cst, int64_t tst, float* cube, float* wout,
                             hipStream_t st);

@@ -19,11 +19,6 @@
 
 namespace cg {
 
-__device__ __noinline__ double chord2_to_d2_exact(double c2) {
-  const double d = 2.0 * asin(0.5 * sqrt(c2));
-  return d * d;
-}
-
 bool mfma_available() { return true; }
 
 template <int NW, int BPW, int KT, int MODE, bool FULL, typename T, int KS>

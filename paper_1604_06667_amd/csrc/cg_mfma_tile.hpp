@@ -106,8 +106,9 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, int nvalid, bool 
 // Software pipeline, one barrier per chunk: while chunk i is on the matrix
 // cores, the same wavefront computes the weight block of chunk i+1 and
 // reloads its data registers with chunk i+1; candidate records run two
-// chunks ahead through a three-deep LDS ring.  Past-the-end candidates point
-// at a row of zeros, so the loads need no bounds selects.  FULL: the channel
+// chunks ahead through a three-deep LDS ring; wavefront 0 finds them by
+// walking the tile's ranges of sorted samples.  Past-the-end candidates
+// point at a row of zeros, so the loads need no bounds selects.  FULL: the channel
 // count is a multiple of CP (no channel bounds checks).
 template <int NW, int BPW, int KT, int MODE, bool FULL, typename T, int KS = 1, bool GL = false>
 __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams kp,
@@ -134,7 +135,6 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.ncap;
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
   const int cl = lane & 31;      // channel within a 32-channel block / target within a 32-target block
   const int kh = lane >> 5;      // which 8 samples of the chunk this lane holds
@@ -186,10 +186,11 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[b][nb][j] = 0.0f;
 
-  const uint64_t cb0 = ldg<GL>(tv.cand_off, tile), cb1 = ldg<GL>(tv.cand_off, tile + 1);
-  const int64_t nchunks = (int64_t)((cb1 - cb0 + MK - 1) / MK);
+  const uint32_t total = (uint32_t)ldg<GL>(tv.ntot, tile);
+  const int64_t nchunks = (int64_t)((total + MK - 1) / MK);
 
-  // candidate record of chunk ch for thread t < MK (NaN / zero row past the end)
+  // candidate record of chunk ch for thread t < MK (NaN / zero row past the
+  // end), found by wavefront 0 through the tile's ranges of sorted samples
   const int64_t zoff = (int64_t)(zrow - data) - c0;   // offset that lands on the zero row
   double rx = nan, ry = nan, rz = nan;
   int64_t rrow = zoff;
@@ -197,17 +198,26 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   // first): a tile and the one below it then reach the rings they share at
   // the same time, while those samples are in L2.
   const bool rev = tv.ntx > 0 && ((tile / tv.ntx) & 1);
-  auto load_rec = [&](int64_t ch) {
-    const uint64_t idx = (uint64_t)ch * MK + t;
-    const uint64_t q = rev ? cb1 - 1 - idx : cb0 + idx;
-    if (ch < nchunks && idx < cb1 - cb0) {
-      rx = ldg<GL>(tv.cxyz, q);
-      ry = ldg<GL>(tv.cxyz, cap + q);
-      rz = ldg<GL>(tv.cxyz, 2 * cap + q);
-      rrow = (int64_t)ldg<GL>(tv.crow, q) * ld;
-    } else {
-      rx = ry = rz = nan;
-      rrow = zoff;   // + channel offsets below stays inside the zero row
+  RangeWindow<GL> rwin;
+  if (wv == 0)
+    rwin.init(tv.rng + 2 * (int64_t)ldg<GL>(tv.roff, tile), ldg<GL>(tv.nr, tile), total, !rev);
+  const int64_t ss = tv.nsorted;
+  auto load_rec = [&](int64_t ch) {   // every lane of wavefront 0
+    rx = ry = rz = nan;
+    rrow = zoff;   // + channel offsets below stays inside the zero row
+    if (ch < nchunks) {
+      const uint32_t i0 = (uint32_t)ch * MK;
+      const uint32_t cnt = total - i0 < (uint32_t)MK ? total - i0 : (uint32_t)MK;
+      if (rev) rwin.cover(total - i0 - cnt, total - 1 - i0, false);
+      else rwin.cover(i0, i0 + cnt - 1, true);
+      const uint32_t idx = i0 + ((uint32_t)t < cnt ? (uint32_t)t : cnt - 1);
+      const int64_t p = rwin.pos(rev ? total - 1 - idx : idx);
+      if ((uint32_t)t < cnt) {
+        rx = ldg<GL>(tv.sx, p);
+        ry = ldg<GL>(tv.sx, ss + p);
+        rz = ldg<GL>(tv.sx, 2 * ss + p);
+        rrow = ((int64_t)ldg<GL>(tv.svals, p) - tv.row0) * ld;
+      }
     }
   };
   auto put_rec = [&](int buf) {
@@ -299,11 +309,14 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   constexpr bool DIRECT = (BF16IN && !F16) || (std::is_same<T, _Float16>::value && F16);
   float raw[BPW][KS][DIRECT ? 1 : 8];
   uint32_t rawp[BPW][KS][4];
+  // Lanes whose channel lies past cend read the last valid channel of the
+  // same row instead (and discard it), so that every address stays inside
+  // the caller's row (or the zero row) whatever the channel count.
   auto load_block = [&](int rb, int b) {
+    const int64_t cofs = bvalid[b] ? cbase + 32 * b : cend - 1;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int64_t* rw = &s_row[rb][16 * s + 8 * kh];
-      const int64_t cofs = cbase + 32 * b;
       if constexpr (DIRECT) {
         const uint16_t* d16 = reinterpret_cast<const uint16_t*>(data);
 #pragma unroll
@@ -314,12 +327,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
       } else {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          if constexpr (GL) {
-            const T v = ldg<GL>(data, rw[i] + cofs);
-            raw[b][s][i] = bvalid[b] ? in_f32<T>(&v) : 0.0f;
-          } else {
-            raw[b][s][i] = bvalid[b] ? in_f32<T>(data + (rw[i] + cofs)) : 0.0f;
-          }
+          const T v = ldg<GL>(data, rw[i] + cofs);
+          raw[b][s][i] = bvalid[b] ? in_f32<T>(&v) : 0.0f;
         }
       }
     }
@@ -327,11 +336,11 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 
   // prologue: records of chunks 0, 1 in LDS, of chunk 2 in registers; the
   // weights and data of chunk 0
-  if (t < MK) {
+  if (wv == 0) {
     load_rec(0);
-    put_rec(0);
+    if (t < MK) put_rec(0);
     load_rec(1);
-    put_rec(1);
+    if (t < MK) put_rec(1);
     load_rec(2);
   }
   __syncthreads();
@@ -347,8 +356,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     const int wc = (int)(ch & 1);                 // weight buffer of chunk ch
     __syncthreads();
     // records: publish chunk ch+2, fetch chunk ch+3
-    if (t < MK) {
-      put_rec(r2);
+    if (wv == 0) {
+      if (t < MK) put_rec(r2);
       load_rec(ch + 3);
     }
     const int kofs = 8 * kh;
@@ -475,7 +484,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       const int64_t slot = tile * kTile + nb * 32 + (lane & 31);
-      float* __restrict__ dst = ov.S + slot;
+      double* __restrict__ dst = ov.S + slot;
 #pragma unroll
       for (int b = 0; b < BPW; ++b) {
 #pragma unroll
@@ -483,8 +492,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
           const int m = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
           const int64_t c = c0 + (wv * BPW + b) * 32 + m;
           if (!FULL && c >= cend) continue;
-          if (add) dst[c * ns] += acc[b][nb][j];
-          else dst[c * ns] = acc[b][nb][j];
+          if (add) dst[c * ns] += (double)acc[b][nb][j];
+          else dst[c * ns] = (double)acc[b][nb][j];
         }
       }
     }

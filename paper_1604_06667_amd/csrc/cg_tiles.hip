@@ -389,7 +389,8 @@ hipError_t launch_tile_windows(const double* caps, const double* txyz, int64_t n
 // Candidate ranges of a grid call: one wavefront per tile, one window slot
 // per lane.  Two binary searches in the ring's sorted segment turn a pixel
 // range into a range of sorted samples; the non-empty ones are compacted in
-// slot (ring) order.
+// slot (ring) order as (first sorted position, first candidate index of the
+// range within the tile), and the tile's candidate count is written.
 
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, uint32_t lo,
                                                     uint32_t hi, uint64_t v) {
@@ -428,12 +429,19 @@ __device__ __forceinline__ void tile_ranges_body(
     const bool h = e > b;
     const uint64_t m = __ballot(h);
     const uint32_t k = written + (uint32_t)__popcll(m & lt);
+    const uint32_t len = e - b;
+    uint32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += v;
+    }
     if (h) {
       ranges[2 * (off + k) + 0] = b;
-      ranges[2 * (off + k) + 1] = e - b;
+      ranges[2 * (off + k) + 1] = (uint32_t)total + (incl - len);
     }
     written += (uint32_t)__popcll(m);
-    total += (uint64_t)wave_sum((double)(e - b));
+    total += (uint64_t)(uint32_t)__shfl((int)incl, 63, 64);
   }
   if (lane == 0) {
     nranges[tile] = written;
@@ -479,137 +487,6 @@ hipError_t launch_tile_ranges(int64_t ntiles, const int32_t* ring_first,
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ntiles), dim3(64), 0, st, ring_first, range_off,
                      win, keys, ring_off, ranges, nranges, ncand);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Expand each tile's ranges into its list of candidates: sorted position and
-// (FULL) input index and unit vector, so that the matrix-core contraction
-// reads its records in one level and contiguously.  The FP32 gathers read
-// the unit vector and input index from the sorted arrays at the position
-// instead, which saves writing and reading them again here.
-
-// One wavefront per tile.  Ranges are taken 64 at a time (one per lane); a
-// wavefront scan of their lengths places them, then every lane writes one
-// candidate per step, finding its range by binary search in LDS.  The data
-// row of a candidate is its value minus row0 (the job's first position).
-template <bool FULL>
-__device__ __forceinline__ void expand_body(const uint32_t* __restrict__ ranges, uint32_t nr,
-                                            uint64_t out, const uint32_t* __restrict__ vals,
-                                            int64_t row0, const double* __restrict__ sx,
-                                            int64_t nsorted, uint32_t* __restrict__ cand,
-                                            uint32_t* __restrict__ crow,
-                                            double* __restrict__ cxyz, int64_t ncap) {
-  __shared__ uint32_t s_start[64], s_b[64];
-  const int lane = threadIdx.x;
-  for (uint32_t k0 = 0; k0 < nr; k0 += 64) {
-    const uint32_t k = k0 + lane;
-    uint32_t b = 0, len = 0;
-    if (k < nr) {
-      b = ranges[2 * k];
-      len = ranges[2 * k + 1];
-    }
-    uint32_t incl = len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t v = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += v;
-    }
-    const uint32_t tot = __shfl(incl, 63, 64);
-    s_start[lane] = incl - len;
-    s_b[lane] = b;
-    __syncthreads();
-    for (uint32_t p = lane; p < tot; p += 64) {
-      // last range whose start is <= p (lengths of the ranges are > 0)
-      int lo = 0, hi = 63;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_start[mid] <= p) lo = mid;
-        else hi = mid - 1;
-      }
-      const uint32_t pos = s_b[lo] + (p - s_start[lo]);
-      const uint64_t o = out + p;
-      cand[o] = pos;
-      if constexpr (FULL) {
-        crow[o] = (uint32_t)((int64_t)vals[pos] - row0);
-        cxyz[o] = sx[pos];
-        cxyz[ncap + o] = sx[nsorted + pos];
-        cxyz[2 * ncap + o] = sx[2 * nsorted + pos];
-      }
-    }
-    out += tot;
-    __syncthreads();
-  }
-}
-
-template <bool FULL>
-__global__ void __launch_bounds__(64) k_expand(const uint64_t* __restrict__ range_off,
-                                               const uint32_t* __restrict__ ranges,
-                                               const uint32_t* __restrict__ nranges,
-                                               const uint64_t* __restrict__ cand_off,
-                                               const uint32_t* __restrict__ vals,
-                                               const double* __restrict__ sx, int64_t nsorted,
-                                               uint32_t* __restrict__ cand,
-                                               uint32_t* __restrict__ crow,
-                                               double* __restrict__ cxyz, int64_t ncap) {
-  const int64_t tile = blockIdx.x;
-  expand_body<FULL>(ranges + 2 * range_off[tile], nranges[tile], cand_off[tile], vals, 0, sx,
-                    nsorted, cand, crow, cxyz, ncap);
-}
-
-__global__ void __launch_bounds__(64) k_batch_expand(
-    const BatchJob* __restrict__ jobs, const int64_t* __restrict__ toff, int njobs,
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ nranges,
-    const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ vals,
-    const double* __restrict__ sx, int64_t nsorted, uint32_t* __restrict__ cand,
-    uint32_t* __restrict__ crow, double* __restrict__ cxyz, int64_t ncap,
-    const int* __restrict__ ovf) {
-  if (*ovf) return;   // candidate buffers too small: nothing is written
-  const int64_t g = blockIdx.x;
-  const int j = job_of(toff, njobs, g);
-  const BatchJob& jb = jobs[j];
-  expand_body<true>(ranges + 2 * (jb.rbase + jb.range_off[g - jb.toff]), nranges[g], cand_off[g],
-                    vals, jb.noff, sx, nsorted, cand, crow, cxyz, ncap);
-}
-
-// ovf[0]: this pass overflows the candidate buffers (cleared every pass);
-// ovf[1]: the same, sticky until the host reads it.
-__global__ void k_batch_guard(const uint64_t* __restrict__ cand_off, int64_t ntiles, int64_t cap,
-                              int* ovf) {
-  if (threadIdx.x == 0 && cand_off[ntiles] > (uint64_t)cap) {
-    ovf[0] = 1;
-    ovf[1] = 1;
-  }
-}
-
-hipError_t launch_batch_guard(const uint64_t* cand_off, int64_t ntiles, int64_t cap, int* ovf,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_guard, dim3(1), dim3(64), 0, st, cand_off, ntiles, cap, ovf);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_expand(const BatchJob* jobs, const int64_t* toff, int njobs, int64_t ntiles,
-                               const uint32_t* ranges, const uint32_t* nranges,
-                               const uint64_t* cand_off, const uint32_t* vals, const double* sx,
-                               int64_t nsorted, uint32_t* cand, uint32_t* crow, double* cxyz,
-                               int64_t ncap, const int* ovf, hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_expand, dim3((unsigned)ntiles), dim3(64), 0, st, jobs, toff, njobs,
-                     ranges, nranges, cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap, ovf);
-  return hipGetLastError();
-}
-
-hipError_t launch_expand(const uint64_t* range_off, const uint32_t* ranges, const uint32_t* nranges,
-                         const uint64_t* cand_off, int64_t ntiles, const uint32_t* vals,
-                         const double* sx, int64_t nsorted, uint32_t* cand, uint32_t* crow,
-                         double* cxyz, int64_t ncap, bool full, hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
-  if (full)
-    hipLaunchKernelGGL(k_expand<true>, dim3((unsigned)ntiles), dim3(64), 0, st, range_off, ranges,
-                       nranges, cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap);
-  else
-    hipLaunchKernelGGL(k_expand<false>, dim3((unsigned)ntiles), dim3(64), 0, st, range_off, ranges,
-                       nranges, cand_off, vals, sx, nsorted, cand, crow, cxyz, ncap);
   return hipGetLastError();
 }
 

@@ -138,21 +138,16 @@ def test_disk_lookup_tiny_grids(nx, ny):
 
 
 def test_disk_lookup_single_pixel():
-    # One target: e_val divides by that target's own value, and its channel
-    # sums of ~350 zero-mean terms cancel by ~50x, so FP32 summation in
-    # either candidate order lands near 1e-6 of it.  The bar here is the
-    # summation's own condition: |R - R_ref| <= 1e-6 * sum|w x| / W, with the
-    # absolute sums from the oracle on |data|; the weight sum and the
-    # neighbour set are held to the usual bars.
+    # One target: e_val divides by that target's own value, whose channel sums
+    # of ~350 zero-mean terms cancel by ~50x.  The FP32 path's products and
+    # sums are FP64, so the candidate order of the disk lookup does not matter
+    # and the plain FP32 bar holds here as it does with the tile lookup.
     wl = synth.config_tiny_grid(1, 1)
     ref = oracle.grid_workload(wl, method="brute")
-    wl_abs = synth.Workload(wl.name, wl.lon, wl.lat, np.abs(wl.data), wl.dtype, wl.target,
-                            wl.kernel, wl.support, hpx_maxres=wl.hpx_maxres)
-    ref_abs = oracle.grid_workload(wl_abs, method="brute")
     g, R, W, (lon, lat, _) = _run(wl)
-    err = np.abs(R - ref["R"])
-    say(f"  |dR|={err.max():.3e} bound={1e-6 * ref_abs['R'].min():.3e}")
-    assert np.all(err <= 1e-6 * ref_abs["R"])
+    ev = oracle.e_val(R, ref["R"], ref["W"])
+    say(f"  e_val={ev:.3e}")
+    assert ev <= TOL32
     assert oracle.e_weights(W, ref["W"]) <= TOL32
     _neighbours(g, wl, lon, lat)
 

@@ -47,7 +47,14 @@ def test_host_argument_errors():
     assert L.cg_create_sightlines(C.byref(h), None, None, 5, 1, None) == _cg.E_INVALID
     p = (C.c_double * 1)(1.0)
     assert L.cg_set_kernel(None, 0, p, 1, 1.0, 1.0) == _cg.E_INVALID
-    assert L.cg_grid(None, None, None, None, 1, 1, 1, None) == _cg.E_INVALID
+    assert L.cg_grid(None, None, None, None, 1, 1, 1, None, 0, None) == _cg.E_INVALID
+    assert L.cg_grid_datacube(None, None, None, None, 1, 1, 1, None, None, None, 0,
+                              None) == _cg.E_INVALID
+    sz = C.c_size_t()
+    assert L.cg_workspace_size(None, 10, C.byref(sz)) == _cg.E_INVALID
+    # an allocator needs both functions (or neither)
+    keep = _cg.ALLOC_FN(lambda n, d, s, c: None)
+    assert L.cg_set_allocator(keep, _cg.FREE_FN(), None) == _cg.E_INVALID
     assert L.cg_set_nside(None, 64) == _cg.E_INVALID
     assert L.cg_set_lookup(None, 1) == _cg.E_INVALID
     a, b = C.c_int64(), C.c_int64()
