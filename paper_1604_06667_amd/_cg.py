@@ -127,7 +127,11 @@ def version() -> str:
 
 # ------------------------------------------------------------- allocator
 
-_ALLOC = {"mode": None, "fns": None}
+_ALLOC = {"mode": None}
+# Every callback pair ever handed to the library stays alive for the life of
+# the process: a handle keeps the allocator it was created with, so its
+# functions must outlive any later change of the allocator.
+_KEEPALIVE = []
 
 
 def _torch_alloc(nbytes, device, stream, ctx):
@@ -146,30 +150,34 @@ def _torch_free(ptr, nbytes, device, ctx):
         pass
 
 
+_TORCH_FNS = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
+_KEEPALIVE.append(_TORCH_FNS)
+
+
 def set_allocator(alloc=None, free=None):
     """Device memory of gridders and batches created from now on
     (cg_set_allocator): ``alloc(nbytes, device, stream) -> int`` (a device
     address, 0 when out of memory) and ``free(ptr, nbytes, device)``, or
-    ``None`` for both to use hipMalloc/hipFree."""
+    ``None`` for both to use hipMalloc/hipFree.  Gridders created earlier
+    keep the allocator they were created with."""
     if (alloc is None) != (free is None):
         raise ValueError("give both alloc and free, or neither")
     if alloc is None:
         fns = (ALLOC_FN(), FREE_FN())
-        _ALLOC["mode"] = "hip"
+        mode = "hip"
     else:
         fns = (ALLOC_FN(lambda n, d, s, c: alloc(n, d, s) or None),
                FREE_FN(lambda p, n, d, c: free(p, n, d)))
-        _ALLOC["mode"] = "custom"
+        mode = "custom"
+    _KEEPALIVE.append(fns)
     check(lib().cg_set_allocator(fns[0], fns[1], None))
-    _ALLOC["fns"] = fns   # the callbacks must outlive every handle that uses them
+    _ALLOC["mode"] = mode
 
 
 def use_torch_allocator():
     """Give gridders and batches created from now on PyTorch's caching
     allocator (the default of this binding)."""
-    fns = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
-    check(lib().cg_set_allocator(fns[0], fns[1], None))
-    _ALLOC["fns"] = fns
+    check(lib().cg_set_allocator(_TORCH_FNS[0], _TORCH_FNS[1], None))
     _ALLOC["mode"] = "torch"
 
 
