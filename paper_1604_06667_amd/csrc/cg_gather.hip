@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   for (uint32_t base = 0; base < total; base += kChunk) {
     const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
     rw.cover(base, base + kmax - 1, true);
-    const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1));
+    const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1), base, base + kmax - 1);
     if (lane < kmax) {
       s_x[lane] = tv.sx[pos];
       s_y[lane] = tv.sx[cap + pos];
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
     const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
     if (wv_id == 0) {
       rw.cover(base, base + kmax - 1, true);
-      const int64_t pos = rw.pos(base + (t < kmax ? t : kmax - 1));
+      const int64_t pos = rw.pos(base + (t < kmax ? t : kmax - 1), base, base + kmax - 1);
       if (t < kmax) {
         s_x[t] = tv.sx[pos];
         s_y[t] = tv.sx[cap + pos];
@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
   for (uint32_t base = 0; base < total; base += kChunk) {
     const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
     rw.cover(base, base + kmax - 1, true);
-    const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1));
+    const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1), base, base + kmax - 1);
     if (lane < kmax) {
       s_x[lane] = tv.sx[pos];
       s_y[lane] = tv.sx[cap + pos];

@@ -83,8 +83,8 @@ __device__ __forceinline__ uint32_t lane_u32(uint32_t v, int l) {
 // s = e = total).  The 64 ranges cover candidates [s of lane 0, e of lane
 // 63).  cover() moves the window (monotonically, in the direction of the
 // walk) until it holds a span of candidates; pos() then maps a candidate
-// index of that span to its sorted position by a binary search over the
-// lanes.  Every lane of the wavefront must take part in both calls.
+// index of that span to its sorted position.  Every lane of the wavefront
+// must take part in both calls.
 template <bool GL>
 struct RangeWindow {
   const uint32_t* rng;
@@ -131,16 +131,21 @@ struct RangeWindow {
       load(nw);
     }
   }
-  // sorted position of candidate q (inside the covered span)
-  __device__ __forceinline__ uint32_t pos(uint32_t q) const {
-    int r = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1) {
-      const uint32_t ev = (uint32_t)__shfl((int)e, r + step - 1, 64);
-      if (ev <= q) r += step;
+  // sorted position of candidate q, where [qlo, qhi] (the same on every
+  // lane) is the covered span: the range holding qlo is found by one
+  // ballot, then each lane steps over the few ranges that start inside the
+  // span (scalar reads of their starts), and two independent shuffles fetch
+  // its range's first position and first candidate index
+  __device__ __forceinline__ uint32_t pos(uint32_t q, uint32_t qlo, uint32_t qhi) const {
+    int r = __popcll(__ballot(e <= qlo));
+    int mine = r;
+    for (int k = r + 1; k < 64; ++k) {
+      const uint32_t sk = lane_u32(s, k);
+      if (sk > qhi) break;
+      if (sk <= q) mine = k;
     }
-    const uint32_t br = (uint32_t)__shfl((int)b, r, 64);
-    const uint32_t sr = (uint32_t)__shfl((int)s, r, 64);
+    const uint32_t br = (uint32_t)__shfl((int)b, mine, 64);
+    const uint32_t sr = (uint32_t)__shfl((int)s, mine, 64);
     return br + (q - sr);
   }
 };

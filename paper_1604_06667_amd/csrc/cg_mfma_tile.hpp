@@ -208,10 +208,10 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     if (ch < nchunks) {
       const uint32_t i0 = (uint32_t)ch * MK;
       const uint32_t cnt = total - i0 < (uint32_t)MK ? total - i0 : (uint32_t)MK;
-      if (rev) rwin.cover(total - i0 - cnt, total - 1 - i0, false);
-      else rwin.cover(i0, i0 + cnt - 1, true);
+      const uint32_t qlo = rev ? total - i0 - cnt : i0, qhi = rev ? total - 1 - i0 : i0 + cnt - 1;
+      rwin.cover(qlo, qhi, !rev);
       const uint32_t idx = i0 + ((uint32_t)t < cnt ? (uint32_t)t : cnt - 1);
-      const int64_t p = rwin.pos(rev ? total - 1 - idx : idx);
+      const int64_t p = rwin.pos(rev ? total - 1 - idx : idx, qlo, qhi);
       if ((uint32_t)t < cnt) {
         rx = ldg<GL>(tv.sx, p);
         ry = ldg<GL>(tv.sx, ss + p);
