@@ -290,6 +290,28 @@ cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* l
                            float* cube_out, float* weights_out, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* cg_grid_datacube for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation) and have no workspace of their own to pass: the same lookup
+ * and contraction, with the per-call workspace taken from a scratch array
+ * of 128 MiB (134,217,728 bytes) that the library holds in static device
+ * memory on every device it runs on, for the life of the process.  The
+ * caller passes inputs and outputs as for cg_grid_datacube.  The call
+ * allocates nothing and does not wait for the device; it takes the address
+ * of its device's scratch on its first call there.  Nothing in the scratch
+ * has to start at zero.  All calls on one device share that device's
+ * scratch and each overwrites it: calls whose work overlaps on one device
+ * (different streams, or different host threads) race; calls queued on one
+ * stream do not.  Errors: those of cg_grid_datacube; CG_E_WORKSPACE when
+ * the samples need more scratch than 128 MiB (cg_workspace_size tells; about
+ * 1.8 million samples, fewer for FP32 grids of up to 16 channels);
+ * CG_E_UNSUPPORTED with the sample-centric lookup (it sizes its lists per
+ * call); CG_E_STATE if the handle's lookup tables were not built. */
+cg_status cg_grid_datacube_noalloc(cg_gridder* g, const double* lon_deg, const double* lat_deg,
+                                   const void* data, int32_t dtype, int64_t nsamples,
+                                   int64_t ld_data, float* cube_out, float* weights_out,
+                                   void* stream);
+
 /* Reset S and W to empty (Sect. 2.1 step 1). */
 cg_status cg_clear(cg_gridder* g, void* stream);
 

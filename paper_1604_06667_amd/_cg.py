@@ -67,6 +67,7 @@ SIGNATURES = {
     "cg_get_datacube": (_i32, [_vp, _vp, _vp]),
     "cg_get_weights": (_i32, [_vp, _vp, _vp]),
     "cg_grid_datacube": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "cg_grid_datacube_noalloc": (_i32, [_vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp]),
     "cg_clear": (_i32, [_vp, _vp]),
     "cg_sync": (_i32, [_vp, _vp]),
     "cg_neighbour_stats": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
@@ -382,6 +383,18 @@ class _Gridder:
                                      _dtype_code(sig), int(lon.shape[0]), int(sig.stride(0)),
                                      _dev_ptr(cube, name="cube"), wp, sp, sn, _stream(stream)))
         return cube, (weights if weights is not False else None)
+
+    def grid_datacube_noalloc(self, lon, lat, signal, cube, weights=None, stream=None):
+        """grid_datacube into caller buffers with the library's static
+        scratch as workspace (cg_grid_datacube_noalloc): no allocation."""
+        pl, pb = self._coords(lon, lat)
+        sig = _data2d(signal, self.nchan)
+        wp = _dev_ptr(weights, name="weights") if weights is not None else None
+        check(lib().cg_grid_datacube_noalloc(self._handle(), pl, pb, C.c_void_p(sig.data_ptr()),
+                                             _dtype_code(sig), int(lon.shape[0]),
+                                             int(sig.stride(0)), _dev_ptr(cube, name="cube"), wp,
+                                             _stream(stream)))
+        return cube, weights
 
     def clear(self, stream=None):
         check(lib().cg_clear(self._handle(), _stream(stream)))

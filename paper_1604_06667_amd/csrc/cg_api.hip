@@ -228,11 +228,12 @@ cg_status check_grid_args(const cg_gridder* g, const double* lon, const double* 
 
 constexpr size_t kMaxProfiled = 4096;
 
+// may_allocate false: events are recorded only into pairs created earlier
 cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
-                   const cg::OutView& ov, hipStream_t st) {
+                   const cg::OutView& ov, hipStream_t st, bool may_allocate = true) {
   const cg::TileView tv = tile_view(g);
   std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
-  if (g->prof && g->nev < kMaxProfiled) {
+  if (g->prof && g->nev < kMaxProfiled && (may_allocate || g->nev < g->ev.size())) {
     if (g->nev == g->ev.size()) {
       hipEvent_t a, b;
       CG_HIP(hipEventCreate(&a), "event");
@@ -257,7 +258,8 @@ cg_status contract(cg_gridder* g, const void* data, int32_t dtype, int64_t ld,
 // of its variant on the library's static scratch), with the workspace at base
 cg_status grid_datacube_ws(cg_gridder* g, const double* lon_deg, const double* lat_deg,
                            const void* data, int32_t dtype, int64_t nsamples, int64_t ld_data,
-                           float* cube_out, float* weights_out, char* base, hipStream_t st) {
+                           float* cube_out, float* weights_out, char* base, hipStream_t st,
+                           bool may_allocate = true) {
   cg_status s = run_lookup(g, lon_deg, lat_deg, nsamples, data, dtype, ld_data, small_c(g), base,
                            st);
   if (s != CG_OK) return s;
@@ -268,7 +270,7 @@ cg_status grid_datacube_ws(cg_gridder* g, const double* lon_deg, const double* l
   ov.slot_target = g->slot_target.as<int32_t>();
   ov.ntarget = g->ntarget;
   ov.mode = cg::ACC_FINAL;
-  return contract(g, data, dtype, ld_data, ov, st);
+  return contract(g, data, dtype, ld_data, ov, st, may_allocate);
 }
 
 cg_status empty_datacube(cg_gridder* g, float* cube_out, float* weights_out, hipStream_t st) {
@@ -294,6 +296,40 @@ cg_gridder* new_gridder() {
   (void)hipGetDevice(&g->device);
   g->alloc = current_allocator(g->device);
   return g;
+}
+
+// ---- the static scratch of cg_grid_datacube_noalloc
+// Every device the library runs on holds one copy of this array for the
+// life of the process.  In host code its name only stands for the symbol:
+// the device address of the current device's copy comes from
+// hipGetSymbolAddress, taken once per device and kept in scratch_ptr.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxScratchDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of `device`'s copy of the scratch array (that device must
+// be current).
+cg_status scratch_of(int device, char** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fail(CG_E_UNSUPPORTED, "device %d: the static scratch serves devices 0-%d", device,
+                kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+    if (!p) return fail(CG_E_DEVICE, "address of the static scratch: null");
+    scratch_ptr[device] = p;
+  }
+  *out = static_cast<char*>(scratch_ptr[device]);
+  return CG_OK;
 }
 
 }  // namespace
@@ -663,6 +699,32 @@ cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* l
   if ((s = call_workspace(g, nsamples, ws, ws_bytes, st, &base)) != CG_OK) return s;
   return grid_datacube_ws(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data, cube_out,
                           weights_out, base, st);
+}
+
+cg_status cg_grid_datacube_noalloc(cg_gridder* g, const double* lon_deg, const double* lat_deg,
+                                   const void* data, int32_t dtype, int64_t nsamples,
+                                   int64_t ld_data, float* cube_out, float* weights_out,
+                                   void* stream) {
+  cg_status s = check_grid_args(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data);
+  if (s != CG_OK) return s;
+  if (!cube_out) return fail(CG_E_INVALID, "null cube_out");
+  if (g->lookup == CG_LOOKUP_DISK)
+    return fail(CG_E_UNSUPPORTED, "the sample-centric lookup sizes its lists per call");
+  if (!g->span_valid) return fail(CG_E_STATE, "lookup tables not built (set_kernel failed)");
+  const size_t need = ws_bytes_for(g, nsamples);
+  if (need > kScratchBytes)
+    return fail(CG_E_WORKSPACE,
+                "%lld samples need %zu bytes of scratch, the static scratch holds %zu "
+                "(pass a workspace to cg_grid_datacube instead)",
+                (long long)nsamples, need, kScratchBytes);
+  if ((s = set_dev(g)) != CG_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  g->fresh = true;
+  if (nsamples == 0) return empty_datacube(g, cube_out, weights_out, st);
+  char* base = nullptr;
+  if ((s = scratch_of(g->device, &base)) != CG_OK) return s;
+  return grid_datacube_ws(g, lon_deg, lat_deg, data, dtype, nsamples, ld_data, cube_out,
+                          weights_out, base, st, false);
 }
 
 cg_status cg_get_datacube(cg_gridder* g, float* out, void* stream) {
