@@ -243,7 +243,7 @@ cg_status cg_set_output_layout(cg_gridder* g, int32_t layout);
  * `nsamples` samples needs with the handle's current kernel, nside and
  * precision: the HEALPix keys with their sort buffers, the ring offsets, the
  * sorted unit vectors and sample records, and for FP32 grids of at most 16
- * channels the sorted data rows.  About 72 bytes per sample plus 4 * nchan
+ * channels the sorted data rows.  About 80 bytes per sample plus 4 * nchan
  * per sample in that last case.  Errors: CG_E_INVALID, CG_E_STATE (no
  * kernel set). */
 cg_status cg_workspace_size(const cg_gridder* g, int64_t nsamples, size_t* bytes);
@@ -304,7 +304,7 @@ cg_status cg_grid_datacube(cg_gridder* g, const double* lon_deg, const double* l
  * (different streams, or different host threads) race; calls queued on one
  * stream do not.  Errors: those of cg_grid_datacube; CG_E_WORKSPACE when
  * the samples need more scratch than 128 MiB (cg_workspace_size tells; about
- * 1.8 million samples, fewer for FP32 grids of up to 16 channels);
+ * 1.6 million samples, fewer for FP32 grids of up to 16 channels);
  * CG_E_UNSUPPORTED with the sample-centric lookup (it sizes its lists per
  * call); CG_E_STATE if the handle's lookup tables were not built. */
 cg_status cg_grid_datacube_noalloc(cg_gridder* g, const double* lon_deg, const double* lat_deg,

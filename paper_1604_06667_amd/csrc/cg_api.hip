@@ -151,7 +151,7 @@ cg_status run_lookup(cg_gridder* g, const double* lon, const double* lat, int64_
   g->sorted_vals = in_tmp ? w.vals2 : w.vals;
   CG_HIP(cg::launch_ring_offsets(g->sorted_keys, n, nside, w.ring_off, st), "ring offsets");
   CG_HIP(cg::launch_permute(g->sorted_vals, w.ring_off + 4 * nside, n, w.rec, data, dtype, ld,
-                            g->nchan, with_data, npack, n, w.sx, w.sdata, st),
+                            g->nchan, with_data, npack, w.srec, w.sdata, st),
          "permute");
   g->last_n = n;
   g->have_ranges = false;
@@ -179,11 +179,8 @@ cg::TileView tile_view(const cg_gridder* g) {
   tv.nr = g->nranges.as<uint32_t>();
   tv.ntot = g->ncand.as<uint64_t>();
   tv.nslots = g->nslots;
-  // the sorted samples of the last lookup (unit vectors SoA, stride last_n)
-  tv.svals = g->sorted_vals;
-  tv.sx = g->ws.sx;
-  tv.nsorted = g->last_n;
-  tv.row0 = 0;
+  // the sorted samples of the last lookup
+  tv.srec = reinterpret_cast<const double4*>(g->ws.srec);
   tv.ntiles = g->ntiles;
   tv.ntx = g->kind == 0 ? g->ntx : 0;
   return tv;

@@ -285,9 +285,7 @@ cg_status contract_part(cg_batch* b, hipStream_t st, bool events) {
   br.ranges = b->ranges.as<uint32_t>();
   br.nranges = b->nranges.as<uint32_t>();
   br.ncand = b->ncand.as<uint64_t>();
-  br.svals = sorted_vals(b);
-  br.sx = b->sx.as<double>();
-  br.nsorted = b->ntot;
+  br.srec = reinterpret_cast<const double4*>(b->sx.as<double>());
   CG_HIP(cg::launch_batch_mfma(dj, b->items.as<cg::BatchItem>(), b->nitems, b->counter.as<int>(),
                                br, b->zrow.p, b->dtype, b->prec, b->shape, b->bpc, st),
          "batch contraction");
@@ -303,7 +301,7 @@ cg_status size_pass(cg_batch* b) {
   if ((s = grow(b, b->keys2, 4 * n, "alloc keys")) != CG_OK) return s;
   if ((s = grow(b, b->vals2, 4 * n, "alloc keys")) != CG_OK) return s;
   if ((s = grow(b, b->hist, 4 * cg::radix_hist_elems(n), "alloc hist")) != CG_OK) return s;
-  if ((s = grow(b, b->sx, 24 * n, "alloc sorted vectors")) != CG_OK) return s;
+  if ((s = grow(b, b->sx, 32 * n, "alloc sorted records")) != CG_OK) return s;
   return CG_OK;
 }
 

@@ -41,10 +41,7 @@ __global__ void __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) k_batch_mfma(
     tv.nslots = jb.nslots;
     tv.ntiles = jb.ntiles;
     tv.ntx = jb.ntx;   // same candidate order as the per-grid kernel
-    tv.svals = br.svals;
-    tv.sx = br.sx;
-    tv.nsorted = br.nsorted;
-    tv.row0 = jb.noff;
+    tv.srec = br.srec;
     OutView ov;
     ov.S = nullptr;
     ov.W = nullptr;

@@ -68,16 +68,16 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   const uint32_t total = (uint32_t)tv.ntot[tile];
   RangeWindow<false> rw;
   rw.init(tv.rng + 2 * tv.roff[tile], tv.nr[tile], total, true);
-  const int64_t cap = tv.nsorted;
   const double thr = 1.0 - 0.5 * kp.cs2 - 2e-15;
   for (uint32_t base = 0; base < total; base += kChunk) {
     const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
     rw.cover(base, base + kmax - 1, true);
     const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1), base, base + kmax - 1);
     if (lane < kmax) {
-      s_x[lane] = tv.sx[pos];
-      s_y[lane] = tv.sx[cap + pos];
-      s_z[lane] = tv.sx[2 * cap + pos];
+      const double4 r = tv.srec[pos];
+      s_x[lane] = r.x;
+      s_y[lane] = r.y;
+      s_z[lane] = r.z;
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
         if (c < nchan) s_d[lane * CMAX + c] = (double)sdata[pos * nchan + c];
@@ -194,7 +194,6 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
   const int64_t c0 = pass * CB;
   const int t = threadIdx.x, lane = t & 63, wv_id = t >> 6;
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.nsorted;
   if (t < kTile) {
     const int64_t slot = tile * kTile + t;
     const double x = tv.txyz[slot];
@@ -226,10 +225,11 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
       rw.cover(base, base + kmax - 1, true);
       const int64_t pos = rw.pos(base + (t < kmax ? t : kmax - 1), base, base + kmax - 1);
       if (t < kmax) {
-        s_x[t] = tv.sx[pos];
-        s_y[t] = tv.sx[cap + pos];
-        s_z[t] = tv.sx[2 * cap + pos];
-        s_row[t] = (int64_t)tv.svals[pos] * ld;
+        const double4 r = tv.srec[pos];
+        s_x[t] = r.x;
+        s_y[t] = r.y;
+        s_z[t] = r.z;
+        s_row[t] = rec_row(r) * ld;
       }
     }
     __syncthreads();
@@ -415,7 +415,6 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
   __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
   __shared__ uint32_t s_n[kChunk];
   const int64_t ns = tv.nslots;
-  const int64_t cap = tv.nsorted;
   const double tx = tv.txyz[slot], ty = tv.txyz[ns + slot], tz = tv.txyz[2 * ns + slot];
   int32_t cnt = 0;
   uint64_t h = 0;
@@ -427,10 +426,11 @@ __global__ void __launch_bounds__(64) k_stats(TileView tv, KernelParams kp,
     rw.cover(base, base + kmax - 1, true);
     const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1), base, base + kmax - 1);
     if (lane < kmax) {
-      s_x[lane] = tv.sx[pos];
-      s_y[lane] = tv.sx[cap + pos];
-      s_z[lane] = tv.sx[2 * cap + pos];
-      s_n[lane] = tv.svals[pos];
+      const double4 r = tv.srec[pos];
+      s_x[lane] = r.x;
+      s_y[lane] = r.y;
+      s_z[lane] = r.z;
+      s_n[lane] = (uint32_t)rec_row(r);
     }
     __syncthreads();
     for (int k = 0; k < kmax; ++k) {

@@ -148,13 +148,14 @@ inline int bits_for(uint64_t v) {
 
 // The per-call scratch of a grid call, carved from one workspace (the
 // caller's or the handle's own): HEALPix keys and sample indices with their
-// sort buffers and histogram, the ring offsets, the sorted unit vectors, the
-// per-sample records of the prep step and, for narrow FP32 grids, the sorted
-// data rows.  Every piece starts on a 256-byte boundary.
+// sort buffers and histogram, the ring offsets, the per-sample records of
+// the prep step (input order) and of the sorted samples (unit vector and
+// input row) and, for narrow FP32 grids, the sorted data rows.  Every piece
+// starts on a 256-byte boundary.
 struct Workspace {
   uint32_t *keys = nullptr, *vals = nullptr, *keys2 = nullptr, *vals2 = nullptr;
   uint32_t *hist = nullptr, *ring_off = nullptr;
-  double *sx = nullptr, *rec = nullptr;
+  double *srec = nullptr, *rec = nullptr;
   float* sdata = nullptr;
 };
 
@@ -175,7 +176,7 @@ inline size_t workspace_layout(int64_t n, int64_t nside, int64_t sdata_chan, cha
   ws.vals2 = (uint32_t*)take(4 * un);
   ws.hist = (uint32_t*)take(4 * cg::radix_hist_elems((int64_t)un));
   ws.ring_off = (uint32_t*)take(4 * (size_t)(4 * nside + 1));
-  ws.sx = (double*)take(24 * un);
+  ws.srec = (double*)take(32 * un);
   ws.rec = (double*)take(32 * un);
   if (sdata_chan > 0) ws.sdata = (float*)take(4 * un * (size_t)sdata_chan);
   if (w) *w = ws;

@@ -47,12 +47,14 @@ struct TileView {
   int64_t nslots;
   int64_t ntiles;
   int64_t ntx;                 // tiles per row of a WCS grid (0: sight lines)
-  // the sorted samples the ranges point into
-  const uint32_t* svals;       // [nsorted] input index (batches: position in the concatenated input)
-  const double* sx;            // [3][nsorted] unit vector
-  int64_t nsorted;
-  int64_t row0;                // input index of the first sample of this job (batches), else 0
+  // the sorted samples the ranges point into: one 32-byte record each, the
+  // unit vector and (as the bits of the fourth double) the sample's row,
+  // i.e. its index in the caller's input (in a batch, the job's input)
+  const double4* srec;
 };
+
+// input row of a sorted sample record
+__device__ __forceinline__ int64_t rec_row(const double4& r) { return __double_as_longlong(r.w); }
 
 // Block -> tile map that keeps consecutive tiles on one XCD: workgroups are
 // dispatched to the 8 XCDs round robin, so block b runs on XCD b % 8; XCD k
@@ -74,6 +76,20 @@ __device__ __forceinline__ void stg(T* p, int64_t i, T v) {
   if constexpr (GL) ((T __attribute__((address_space(1)))*)p)[i] = v;
   else p[i] = v;
 }
+// sorted sample record i (one 32-byte load)
+template <bool GL>
+__device__ __forceinline__ double4 ld_rec(const double4* p, int64_t i) {
+  if constexpr (GL) {
+    typedef double d2g_t __attribute__((ext_vector_type(2)));
+    const d2g_t __attribute__((address_space(1)))* q =
+        (const d2g_t __attribute__((address_space(1)))*)(p + i);
+    const d2g_t a = q[0], b = q[1];
+    return make_double4(a.x, a.y, b.x, b.y);
+  } else {
+    return p[i];
+  }
+}
+
 __device__ __forceinline__ uint32_t lane_u32(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
@@ -268,9 +284,10 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32
 size_t radix_hist_elems(int64_t n);   // includes 256 digit totals
 hipError_t launch_ring_offsets(const uint32_t* keys, int64_t n, int64_t nside, uint32_t* ring_off,
                                hipStream_t st);
+// srec: one record per sorted sample (unit vector, input row as int64 bits)
 hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int64_t n,
                           const double* rec, const void* data, int dtype, int64_t ld,
-                          int64_t nchan, bool with_data, int npack, int64_t cap, double* sx,
+                          int64_t nchan, bool with_data, int npack, double* srec,
                           float* sdata, hipStream_t st);
 hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st);
 // the same over many blocks; scratch holds scan_u64_wide_scratch(n) values
@@ -401,7 +418,7 @@ hipError_t launch_batch_ring_offsets(const BatchJob* jobs, const int64_t* rooff,
                                      int64_t nentries, const uint32_t* keys, uint32_t* ring_off,
                                      hipStream_t st);
 hipError_t launch_batch_permute(const BatchJob* jobs, const int64_t* noff, int njobs, int64_t ntot,
-                                const uint32_t* vals, const uint32_t* ring_off, double* sx,
+                                const uint32_t* vals, const uint32_t* ring_off, double* srec,
                                 hipStream_t st);
 hipError_t launch_batch_tile_ranges(const BatchJob* jobs, const int64_t* toff, int njobs,
                                     int64_t ntiles, const uint32_t* keys, const uint32_t* ring_off,
@@ -413,9 +430,7 @@ struct BatchRanges {
   const uint32_t* ranges;
   const uint32_t* nranges;
   const uint64_t* ncand;
-  const uint32_t* svals;       // sorted positions in the concatenated input
-  const double* sx;            // [3][nsorted] sorted unit vectors
-  int64_t nsorted;
+  const double4* srec;         // sorted records (rows local to each job)
 };
 // Persistent contraction over a queue of items; shape 0..3 selects the
 // workgroup (8 or 4 wavefronts, 1 or 2 channel blocks each: at most

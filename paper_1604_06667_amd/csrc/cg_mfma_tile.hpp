@@ -106,10 +106,13 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, int nvalid, bool 
 // Software pipeline, one barrier per chunk: while chunk i is on the matrix
 // cores, the same wavefront computes the weight block of chunk i+1 and
 // reloads its data registers with chunk i+1; candidate records run two
-// chunks ahead through a three-deep LDS ring; wavefront 0 finds them by
-// walking the tile's ranges of sorted samples.  Past-the-end candidates
-// point at a row of zeros, so the loads need no bounds selects.  FULL: the channel
+// chunks ahead through a three-deep LDS ring; wavefront 0 loads them from the
+// tile's list of sorted positions.  Past-the-end candidates point at a row
+// of zeros, so the loads need no bounds selects.  FULL: the channel
 // count is a multiple of CP (no channel bounds checks).
+constexpr int kListCands = 4096;    // candidates of a tile listed in LDS
+constexpr int kListRanges = 512;    // ranges of a tile listed in LDS
+
 template <int NW, int BPW, int KT, int MODE, bool FULL, typename T, int KS = 1, bool GL = false>
 __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams kp,
                                           const T* __restrict__ data, const T* __restrict__ zrow,
@@ -132,6 +135,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   __shared__ double s_wfin[2][kTile];
   __shared__ double s_tg[kTile][3];                    // target unit vectors
   __shared__ float s_ax[(KT == 1 || KT == 2) ? kTile : 1][3];   // major axis at the target (elliptical)
+  __shared__ uint32_t s_pos[kListCands];               // sorted positions of the tile's candidates
+  __shared__ uint32_t s_rb[kListRanges], s_rs[kListRanges];
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t ns = tv.nslots;
@@ -188,9 +193,35 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
 
   const uint32_t total = (uint32_t)ldg<GL>(tv.ntot, tile);
   const int64_t nchunks = (int64_t)((total + MK - 1) / MK);
+  const uint32_t nr = ldg<GL>(tv.nr, tile);
+  const uint32_t* rng = tv.rng + 2 * (int64_t)ldg<GL>(tv.roff, tile);
+
+  // The tile's candidates in walk order: a tile of at most kListCands
+  // candidates in kListRanges ranges has its sorted positions listed in LDS
+  // at the start (all threads, one binary search over the ranges' starts per
+  // candidate), so the loader reads them with one LDS access; a longer tile
+  // is walked by wavefront 0 through a window of 64 ranges.
+  const bool listed = total <= (uint32_t)kListCands && nr <= (uint32_t)kListRanges;
+  if (listed) {
+    for (uint32_t i = t; i < nr; i += NW * 64) {
+      s_rb[i] = ldg<GL>(rng, 2 * (int64_t)i);
+      s_rs[i] = ldg<GL>(rng, 2 * (int64_t)i + 1);
+    }
+    __syncthreads();
+    for (uint32_t q = t; q < total; q += NW * 64) {
+      uint32_t lo = 0, hi = nr - 1;   // last range whose first candidate index is <= q
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_rs[mid] <= q) lo = mid;
+        else hi = mid - 1;
+      }
+      s_pos[q] = s_rb[lo] + (q - s_rs[lo]);
+    }
+    __syncthreads();
+  }
 
   // candidate record of chunk ch for thread t < MK (NaN / zero row past the
-  // end), found by wavefront 0 through the tile's ranges of sorted samples
+  // end)
   const int64_t zoff = (int64_t)(zrow - data) - c0;   // offset that lands on the zero row
   double rx = nan, ry = nan, rz = nan;
   int64_t rrow = zoff;
@@ -199,24 +230,29 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   // the same time, while those samples are in L2.
   const bool rev = tv.ntx > 0 && ((tile / tv.ntx) & 1);
   RangeWindow<GL> rwin;
-  if (wv == 0)
-    rwin.init(tv.rng + 2 * (int64_t)ldg<GL>(tv.roff, tile), ldg<GL>(tv.nr, tile), total, !rev);
-  const int64_t ss = tv.nsorted;
+  if (wv == 0 && !listed) rwin.init(rng, nr, total, !rev);
   auto load_rec = [&](int64_t ch) {   // every lane of wavefront 0
     rx = ry = rz = nan;
     rrow = zoff;   // + channel offsets below stays inside the zero row
     if (ch < nchunks) {
       const uint32_t i0 = (uint32_t)ch * MK;
       const uint32_t cnt = total - i0 < (uint32_t)MK ? total - i0 : (uint32_t)MK;
-      const uint32_t qlo = rev ? total - i0 - cnt : i0, qhi = rev ? total - 1 - i0 : i0 + cnt - 1;
-      rwin.cover(qlo, qhi, !rev);
       const uint32_t idx = i0 + ((uint32_t)t < cnt ? (uint32_t)t : cnt - 1);
-      const int64_t p = rwin.pos(rev ? total - 1 - idx : idx, qlo, qhi);
+      const uint32_t q = rev ? total - 1 - idx : idx;
+      int64_t p;
+      if (listed) {
+        p = s_pos[q];
+      } else {
+        const uint32_t qlo = rev ? total - i0 - cnt : i0, qhi = rev ? total - 1 - i0 : i0 + cnt - 1;
+        rwin.cover(qlo, qhi, !rev);
+        p = rwin.pos(q, qlo, qhi);
+      }
       if ((uint32_t)t < cnt) {
-        rx = ldg<GL>(tv.sx, p);
-        ry = ldg<GL>(tv.sx, ss + p);
-        rz = ldg<GL>(tv.sx, 2 * ss + p);
-        rrow = ((int64_t)ldg<GL>(tv.svals, p) - tv.row0) * ld;
+        const double4 r = ld_rec<GL>(tv.srec, p);
+        rx = r.x;
+        ry = r.y;
+        rz = r.z;
+        rrow = rec_row(r) * ld;
       }
     }
   };

@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(256) k_batch_permute(const BatchJob* __restric
                                                        int64_t ntot,
                                                        const uint32_t* __restrict__ vals,
                                                        const uint32_t* __restrict__ ring_off,
-                                                       double* __restrict__ sx) {
+                                                       double4* __restrict__ srec) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ntot) return;
   const int j = job_of(noff, njobs, p);
@@ -431,17 +431,16 @@ __global__ void __launch_bounds__(256) k_batch_permute(const BatchJob* __restric
   double sa, ca, sd, cd;
   sincos(am * (hpx::kPi / 180.0), &sa, &ca);
   sincos(jb.lat[src] * (hpx::kPi / 180.0), &sd, &cd);
-  sx[p] = cd * ca;
-  sx[ntot + p] = cd * sa;
-  sx[2 * ntot + p] = sd;
+  // the row is the job's own input index
+  srec[p] = make_double4(cd * ca, cd * sa, sd, __longlong_as_double(src));
 }
 
 hipError_t launch_batch_permute(const BatchJob* jobs, const int64_t* noff, int njobs, int64_t ntot,
-                                const uint32_t* vals, const uint32_t* ring_off, double* sx,
+                                const uint32_t* vals, const uint32_t* ring_off, double* srec,
                                 hipStream_t st) {
   if (ntot <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_permute, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st,
-                     jobs, noff, njobs, ntot, vals, ring_off, sx);
+                     jobs, noff, njobs, ntot, vals, ring_off, reinterpret_cast<double4*>(srec));
   return hipGetLastError();
 }
 
@@ -482,16 +481,14 @@ __global__ void __launch_bounds__(256) k_permute(const uint32_t* __restrict__ va
                                                  const double4* __restrict__ rec,
                                                  const T* __restrict__ data, int64_t ld,
                                                  int64_t nchan, int with_data, int npack,
-                                                 int64_t cap, double* __restrict__ sx,
+                                                 double4* __restrict__ srec,
                                                  float* __restrict__ sdata) {
   const int64_t nvalid = (int64_t)(*nvalid_p);
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nvalid) return;
   const int64_t src = vals[p];
   const double4 r = rec[src];
-  sx[p] = r.x;
-  sx[cap + p] = r.y;
-  sx[2 * cap + p] = r.z;
+  srec[p] = make_double4(r.x, r.y, r.z, __longlong_as_double(src));
   if (with_data) {
     if (npack > 0) {
       // channels carried in the record
@@ -512,7 +509,7 @@ __global__ void __launch_bounds__(256) k_permute(const uint32_t* __restrict__ va
 
 hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int64_t n,
                           const double* rec, const void* data, int dtype, int64_t ld,
-                          int64_t nchan, bool with_data, int npack, int64_t cap, double* sx,
+                          int64_t nchan, bool with_data, int npack, double* srec,
                           float* sdata, hipStream_t st) {
   // nvalid_dev points at the number of valid samples (ring_off[4 nside]);
   // the grid covers all n sorted entries and threads past it return.
@@ -520,26 +517,27 @@ hipError_t launch_permute(const uint32_t* vals, const uint32_t* nvalid_dev, int6
   const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
   const int wd = with_data ? 1 : 0;
   const double4* r = reinterpret_cast<const double4*>(rec);
+  double4* sr = reinterpret_cast<double4*>(srec);
   switch (dtype) {
     case 0:
       hipLaunchKernelGGL((k_permute<double, false>), grid, blk, 0, st, vals, nvalid_dev, r,
-                         (const double*)data, ld, nchan, wd, npack, cap, sx, sdata);
+                         (const double*)data, ld, nchan, wd, npack, sr, sdata);
       break;
     case 1:
       if (wd && nchan % 4 == 0 && ld % 4 == 0 && ((uintptr_t)data & 15) == 0)
         hipLaunchKernelGGL((k_permute<float, true>), grid, blk, 0, st, vals, nvalid_dev, r,
-                           (const float*)data, ld, nchan, wd, npack, cap, sx, sdata);
+                           (const float*)data, ld, nchan, wd, npack, sr, sdata);
       else
         hipLaunchKernelGGL((k_permute<float, false>), grid, blk, 0, st, vals, nvalid_dev, r,
-                           (const float*)data, ld, nchan, wd, npack, cap, sx, sdata);
+                           (const float*)data, ld, nchan, wd, npack, sr, sdata);
       break;
     case 2:
       hipLaunchKernelGGL((k_permute<_Float16, false>), grid, blk, 0, st, vals, nvalid_dev, r,
-                         (const _Float16*)data, ld, nchan, wd, npack, cap, sx, sdata);
+                         (const _Float16*)data, ld, nchan, wd, npack, sr, sdata);
       break;
     default:
       hipLaunchKernelGGL((k_permute<uint16_t, false>), grid, blk, 0, st, vals, nvalid_dev, r,
-                         (const uint16_t*)data, ld, nchan, wd, npack, cap, sx, sdata);
+                         (const uint16_t*)data, ld, nchan, wd, npack, sr, sdata);
       break;
   }
   return hipGetLastError();

@@ -54,7 +54,7 @@ def test_caller_workspace(prec):
     lon, lat, d = to_device(wl)
     n = lon.shape[0]
     need = g.workspace_size(n)
-    assert need >= 72 * n
+    assert need >= 80 * n
     c0, w0 = g.grid_datacube(lon, lat, d)
     ws = g.workspace(n)
     c1, w1 = g.grid_datacube(lon, lat, d, ws=ws)
