@@ -9,7 +9,9 @@ region starts.
 
 Workloads (``--workload``; all synthetic, seeded):
 
-* ``cube`` (default): 1,000,000 samples on a jittered raster scan (row
+* ``all`` (default): ``cube`` as the headline line, with ``batched`` and
+  ``sightlines`` as objects under ``workloads`` in the same line.
+* ``cube``: 1,000,000 samples on a jittered raster scan (row
   spacing 1', jitter 0.2') over 10x10 deg around (120, 30) deg, 1024 FP32
   channels of Gaussian spectral lines plus noise, onto a 600x600 SIN grid at
   1'; Gaussian kernel sigma 1.5', support 3 sigma.  BF16 matrix-core
@@ -31,7 +33,9 @@ Workloads (``--workload``; all synthetic, seeded):
 
 Prints one JSON line.  ``value`` = sample-channel contributions per second =
 (number of (target, sample) pairs with d <= support) x channels / time per
-step.
+step.  Each workload's ``cpu_baseline`` is the FP64 oracle on forked worker
+processes over a stated sample of its targets, which also yields ``e_val``
+and ``e_W`` of every GPU result there.
 """
 from __future__ import annotations
 
@@ -124,55 +128,166 @@ def time_path(g, lon, lat, data, cube, weights, steps, warmup):
     return (t1 - t0) * 1e3 / steps, (kms / max(nl, 1)), nl
 
 
-def oracle_sample(wl, tidx, margin_deg):
-    """Samples that can reach the targets tidx (a compact region), and the
-    oracle's result for those targets; returns (result, seconds, nsamples)."""
+# ------------------------------------------------------------ CPU baseline
+#
+# The oracle (FP64 NumPy/SciPy: cKDTree ball query, Vincenty distance, one
+# sparse product per block of targets) runs unchanged in forked worker
+# processes, one band of targets per task; each task also compares its band of
+# every GPU cube with the oracle (block pieces of e_val), so whole cubes are
+# checked without gathering the oracle's result in one process.
+
+PAPER_CPU = {"value": 1.7e7, "unit": "contributions/s", "cores": 16,
+             "note": ("Sect. 4, Example 1: 1e8 samples gridded in about 67 s on the authors' "
+                      "16-core workstation; contributions derived with a 3-sigma support "
+                      "(about 11.5 target pixels per sample); other workload, other machine")}
+
+_ORACLE_JOBS = []
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_workers():
+    """Worker processes for the oracle: the host's cores, at most 15 (one
+    GPU's 16-core share, less the parent process that holds the GPU)."""
+    n = os.cpu_count() or 1
+    try:
+        n = min(n, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        pass
+    return max(1, min(n, 15))
+
+
+def samples_near(slon, slat, tlon, tlat, reach):
+    """Indices of the samples inside a lon/lat box holding every point within
+    ``reach`` degrees of the targets (the whole latitude band if the box nears
+    a pole or would span the full circle)."""
+    lat_hi = min(90.0, float(tlat.max()) + reach)
+    lat_lo = max(-90.0, float(tlat.min()) - reach)
+    clat = math.cos(math.radians(max(abs(lat_lo), abs(lat_hi))))
+    rl = math.degrees(math.atan2(np.sin(np.radians(tlon)).mean(), np.cos(np.radians(tlon)).mean()))
+    dl = ((tlon - rl + 180.0) % 360.0) - 180.0
+    half = max(abs(dl.min()), abs(dl.max())) + reach / max(clat, 1e-6)
+    sel = (slat >= lat_lo) & (slat <= lat_hi)
+    if lat_hi < 89.9 and lat_lo > -89.9 and half < 180.0:
+        sel &= np.abs(((slon - rl + 180.0) % 360.0) - 180.0) <= half
+    return np.nonzero(sel)[0]
+
+
+def oracle_job(wl, tidx, cubes, weights, tsort=None):
+    """Host copies for one workload: the sampled targets (in band order), the
+    samples that can reach them (data as FP32; the GPU inputs are FP32 or
+    BF16, so this is exact), and each GPU cube's [C][T] values there."""
     import oracle
     import torch
     tlon, tlat = oracle.targets_of(wl)
+    tidx = np.asarray(tidx, dtype=np.int64)
+    ok = np.isfinite(tlon[tidx]) & np.isfinite(tlat[tidx])
+    tidx = tidx[ok]
+    if tsort is not None:
+        tidx = tidx[np.argsort(tsort(tlon[tidx], tlat[tidx]), kind="stable")]
     bl, bb = tlon[tidx], tlat[tidx]
-    ok = np.isfinite(bl) & np.isfinite(bb)
-    bl, bb, tidx = bl[ok], bb[ok], tidx[ok]
-    m = wl.support + margin_deg
-    lat_hi = min(90.0, bb.max() + m)
-    lat_lo = max(-90.0, bb.min() - m)
-    clat = math.cos(math.radians(max(abs(lat_lo), abs(lat_hi))))
-    ref_lon = math.degrees(math.atan2(np.sin(np.radians(bl)).mean(), np.cos(np.radians(bl)).mean()))
-    dl = ((bl - ref_lon + 180.0) % 360.0) - 180.0
-    half = max(abs(dl.min()), abs(dl.max())) + m / max(clat, 1e-6)
-    sl = ((wl.lon - ref_lon + 180.0) % 360.0) - 180.0
-    sel = (wl.lat >= lat_lo) & (wl.lat <= lat_hi)
-    if lat_hi < 89.9 and lat_lo > -89.9 and half < 180.0:
-        sel &= np.abs(sl) <= half
-    sidx = np.nonzero(sel)[0]
+    sidx = samples_near(wl.lon, wl.lat, bl, bb, wl.support + 0.05)
     if isinstance(wl.data, np.ndarray):
-        data = wl.data[sidx].astype(np.float64)
+        data = np.ascontiguousarray(wl.data[sidx], dtype=np.float32)
     else:
-        data = wl.data[torch.as_tensor(sidx, device=wl.data.device)].to("cpu", torch.float64).numpy()
-    t0 = time.perf_counter()
-    ref = oracle.grid_kdtree(wl.lon[sidx], wl.lat[sidx], data, bl, bb, wl.kernel, wl.support)
-    dt = time.perf_counter() - t0
-    return ref, tidx, dt, sidx.size
-
-
-def cpu_baseline(wl, tidx, desc, cubes, margin_deg=0.02):
-    """Oracle (FP64, cKDTree candidates + Vincenty, one thread) on a bounded
-    sample of the workload's targets; also the e_val of each GPU cube there."""
-    import oracle
-    import torch
-    ref, tidx, dt, ns = oracle_sample(wl, tidx, margin_deg)
-    contrib = float(ref["count"].sum()) * wl.nchan
-    errs = {}
+        data = wl.data[torch.as_tensor(sidx, device=wl.data.device)].to("cpu", torch.float32).numpy()
+    ti = None
+    hc, hw = {}, {}
     for prec, cube in cubes.items():
-        R = cube.reshape(wl.nchan, -1)[:, torch.as_tensor(tidx, device=cube.device)]
-        errs[prec] = float(f"{oracle.e_val(R.to('cpu', torch.float64).numpy(), ref['R'], ref['W']):.3e}")
-    cpu = {"value": contrib / dt, "unit": "contributions/s", "cores": 1, "kind": "oracle",
-           "sample": (f"{desc}: {tidx.size} targets with the {ns} samples that can reach "
-                      f"them; FP64 NumPy/SciPy (cKDTree ball query + Vincenty), single "
-                      f"thread, {dt:.1f} s"),
-           "seconds": round(dt, 2)}
-    log(f"cpu oracle: {cpu['value']:.3e} contributions/s in {dt:.1f}s; e_val {errs}")
-    return cpu, errs
+        if ti is None or ti.device != cube.device:
+            ti = torch.as_tensor(tidx, device=cube.device)
+        hc[prec] = cube.reshape(wl.nchan, -1)[:, ti].to("cpu", torch.float32).numpy()
+        hw[prec] = weights[prec].reshape(-1)[ti].to("cpu", torch.float32).numpy()
+    return {"lon": np.ascontiguousarray(wl.lon[sidx]), "lat": np.ascontiguousarray(wl.lat[sidx]),
+            "data": data, "tlon": bl, "tlat": bb, "kernel": wl.kernel, "support": wl.support,
+            "nchan": wl.nchan, "cubes": hc, "weights": hw}
+
+
+def _oracle_task(task):
+    import oracle
+    wi, a, b = task
+    J = _ORACLE_JOBS[wi]
+    tl, tb = J["tlon"][a:b], J["tlat"][a:b]
+    s = samples_near(J["lon"], J["lat"], tl, tb, J["support"] + 0.02)
+    t0 = time.perf_counter()
+    ref = oracle.grid_kdtree(J["lon"][s], J["lat"][s], J["data"][s].astype(np.float64), tl, tb,
+                             J["kernel"], J["support"])
+    dt = time.perf_counter() - t0
+    out = {"pairs": int(ref["count"].sum()), "seconds": dt, "parts": {}, "e_W": {}, "err": None}
+    for prec, cube in J["cubes"].items():
+        try:
+            out["parts"][prec] = oracle.e_val_parts(cube[:, a:b], ref["R"], ref["W"])
+            out["e_W"][prec] = oracle.e_weights(J["weights"][prec][a:b], ref["W"])
+        except AssertionError as e:
+            out["err"] = f"{prec}: {e}"
+    return wi, out
+
+
+def cpu_baseline(jobs, desc, tasks_per_worker=3):
+    """Time the oracle over the sampled targets of ``jobs`` (a list of
+    ``oracle_job`` dicts) on a fork pool; returns the cpu_baseline object and
+    e_val / e_W of each GPU cube (max over jobs; each job's channel norms are
+    its own)."""
+    import multiprocessing as mp
+    import oracle
+    global _ORACLE_JOBS
+    _ORACLE_JOBS = jobs
+    P = oracle_workers()
+    work = [len(J["tlon"]) * J["nchan"] for J in jobs]
+    ntask = P * tasks_per_worker
+    tasks = []
+    for wi, J in enumerate(jobs):
+        T = len(J["tlon"])
+        k = max(1, min(T, int(round(ntask * work[wi] / max(sum(work), 1)))))
+        cuts = np.linspace(0, T, k + 1).astype(np.int64)
+        tasks += [(wi, int(x), int(y)) for x, y in zip(cuts[:-1], cuts[1:]) if y > x]
+    tasks.sort(key=lambda t: -(t[2] - t[1]) * jobs[t[0]]["nchan"])
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(P) as pool:
+        res = list(pool.imap_unordered(_oracle_task, tasks, chunksize=1))
+    wall = time.perf_counter() - t0
+    pairs = [0] * len(jobs)
+    parts = [dict() for _ in jobs]
+    ew, errs = {}, []
+    for wi, o in res:
+        pairs[wi] += o["pairs"]
+        for prec, pt in o["parts"].items():
+            parts[wi].setdefault(prec, []).append(pt)
+        for prec, v in o["e_W"].items():
+            ew[prec] = max(ew.get(prec, 0.0), v)
+        if o["err"]:
+            errs.append(f"job {wi}: {o['err']}")
+    contrib = float(sum(p * J["nchan"] for p, J in zip(pairs, jobs)))
+    e_val = {}
+    for wi in range(len(jobs)):
+        for prec, pts in parts[wi].items():
+            e_val[prec] = max(e_val.get(prec, 0.0), oracle.e_val_combine(pts))
+    e_val = {p: float(f"{v:.3e}") for p, v in e_val.items()}
+    ew = {p: float(f"{v:.3e}") for p, v in ew.items()}
+    nt = sum(len(J["tlon"]) for J in jobs)
+    worker_s = sum(o["seconds"] for _, o in res)
+    cpu = {"value": contrib / wall, "unit": "contributions/s", "cores": P, "kind": "oracle",
+           "sample": (f"{desc}: {nt} targets, {int(sum(pairs))} pairs, {len(tasks)} bands of "
+                      f"targets on {P} forked workers; FP64 NumPy/SciPy (cKDTree ball query + "
+                      f"Vincenty + sparse product), {wall:.1f} s wall, {worker_s:.1f} s in the "
+                      f"oracle summed over workers"),
+           "seconds": round(wall, 2), "model": cpu_model(), "cpu_count": os.cpu_count(),
+           "paper": PAPER_CPU}
+    _ORACLE_JOBS = []
+    log(f"cpu oracle: {cpu['value']:.3e} contributions/s in {wall:.1f}s on {P} workers; "
+        f"e_val {e_val} e_W {ew}")
+    if errs:
+        log("oracle comparison failures: " + "; ".join(errs[:8]))
+    return cpu, {"e_val": e_val, "e_W": ew, **({"mask_errors": errs[:8]} if errs else {})}
 
 
 def device_inputs(wl, dev):
@@ -257,12 +372,12 @@ def run_cube(a, dev):
     weights = torch.empty((600, 600), dtype=torch.float32, device=dev)
     ms, kms, nl = time_path(g, lon, lat, data, cube, weights, a.steps, a.warmup)
     log(f"{headline}: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
-    cubes = {headline: cube.clone()}
+    cubes, wmaps = {headline: cube.clone()}, {headline: weights.clone()}
     extra = {}
     if headline != "fp32" and not a.no_compare:
         g.set_precision("fp32")
         ms32, kms32, _ = time_path(g, lon, lat, data, cube, weights, max(2, a.steps // 2), 1)
-        cubes["fp32"] = cube.clone()
+        cubes["fp32"], wmaps["fp32"] = cube.clone(), weights.clone()
         extra["fp32_path"] = {"value": contributions / (ms32 / 1e3), "ms_per_step": round(ms32, 4),
                               "kernel_ms": round(kms32, 4)}
         extra["speedup_vs_fp32"] = round(ms32 / ms, 3)
@@ -274,12 +389,15 @@ def run_cube(a, dev):
         roof = roof_hbm(alg_bytes, kms, f"contraction_{headline}")
     cpu = None
     if not a.no_cpu:
-        b = a.cpu_block
+        b = a.cpu_block if 0 < a.cpu_block < 600 else 600
         x0 = (600 - b) // 2
         xs, ys = np.meshgrid(np.arange(x0, x0 + b), np.arange(x0, x0 + b))
-        cpu, errs = cpu_baseline(wl, (ys * 600 + xs).ravel(),
-                                 f"central {b}x{b} targets of the 600x600 grid", cubes)
-        extra["e_val"] = errs
+        what = "every target of the 600x600 grid" if b == 600 else f"central {b}x{b} targets"
+        job = oracle_job(wl, (ys * 600 + xs).ravel(), cubes, wmaps)
+        del cubes, wmaps
+        cpu, errs = cpu_baseline([job], what)
+        del job
+        extra.update(errs)
     out = base_line(a, ("spectral cube: 1,000,000 jittered-raster samples x 1024 FP32 channels "
                         "-> 600x600 SIN grid at 1', gauss1d sigma 1.5', support 4.5'"),
                     contributions / (ms / 1e3), ms, DT[headline],
@@ -312,8 +430,9 @@ def run_map(a, dev):
     roof["alg_bytes"] = int(wl.nsamples * (wl.nchan * 8 + 16) + nx * ny * (wl.nchan * 4 + 4))
     cpu, extra = None, {}
     if not a.no_cpu:
-        cpu, errs = cpu_baseline(wl, np.arange(nx * ny), f"all {nx}x{ny} targets", {"fp32": cube})
-        extra["e_val"] = errs
+        cpu, errs = cpu_baseline([oracle_job(wl, np.arange(nx * ny), {"fp32": cube},
+                                             {"fp32": weights})], f"all {nx}x{ny} targets")
+        extra.update(errs)
     out = base_line(a, ("plain map: 20,000 samples x 1 FP64 channel -> 96x96 CAR at 2', "
                         "gauss1d sigma 1.5', support 4.5', nside 4096"),
                     contributions / (ms / 1e3), ms, "f32",
@@ -348,10 +467,10 @@ def run_allsky(a, dev):
         k = 768
         y0, x0 = ny // 2 - k // 2, nx // 2 - k // 2
         xs, ys = np.meshgrid(np.arange(x0, x0 + k), np.arange(y0, y0 + k))
-        cpu, errs = cpu_baseline(wl, (ys * nx + xs).ravel(),
-                                 f"{k}x{k} targets across the 0/360 seam on the equator",
-                                 {"fp32": cube})
-        extra["e_val"] = errs
+        cpu, errs = cpu_baseline([oracle_job(wl, (ys * nx + xs).ravel(), {"fp32": cube},
+                                             {"fp32": weights})],
+                                 f"{k}x{k} targets across the 0/360 seam on the equator")
+        extra.update(errs)
     out = base_line(a, ("all-sky map: 12,000,000 uniform samples x 8 FP32 channels -> 4320x2160 "
                         "CAR at 5', gauss1d sigma 6', support 18', nside 1024"),
                     contributions / (ms / 1e3), ms, "f32",
@@ -385,9 +504,9 @@ def run_healpix(a, dev):
         import oracle
         tl, tb = oracle.targets_of(wl)
         tidx = np.nonzero((tb > 0.0) & (tb < 40.0) & (tl > 170.0) & (tl < 230.0))[0]
-        cpu, errs = cpu_baseline(wl, tidx, "the map pixels with 0 < lat < 40 and 170 < lon < 230 deg",
-                                 {"fp32": cube})
-        extra["e_val"] = errs
+        cpu, errs = cpu_baseline([oracle_job(wl, tidx, {"fp32": cube}, {"fp32": weights})],
+                                 "the map pixels with 0 < lat < 40 and 170 < lon < 230 deg")
+        extra.update(errs)
     nside = wl.target["nside"]
     out = base_line(a, (f"HEALPix map (App. A.1): {wl.nsamples:,} uniform samples x {wl.nchan} "
                         f"FP32 channels (point sources + noise) -> the {nt:,} pixel centres of "
@@ -417,7 +536,7 @@ def run_sightlines(a, dev):
     # ([C][T]) cube is timed beside it for BF16
     g.set_output_layout("target")
     cube = torch.empty((nt, wl.nchan), dtype=torch.float32, device=dev)
-    res, cubes = {}, {}
+    res, cubes, wmaps = {}, {}, {}
     for prec in ["bf16", "fp16", "fp32"]:
         if prec == "fp32" and a.no_compare:
             continue
@@ -426,6 +545,7 @@ def run_sightlines(a, dev):
         ms, kms, nl = time_path(g, lon, lat, data, cube, weights, st, 1 if prec == "fp32" else a.warmup)
         res[prec] = (ms, kms)
         cubes[prec] = cube.t().contiguous()
+        wmaps[prec] = weights.clone()
         log(f"{prec}: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
     g.set_precision("bf16")
     g.set_output_layout("channel")
@@ -445,11 +565,15 @@ def run_sightlines(a, dev):
         extra["speedup_vs_fp32"] = round(res["fp32"][0] / ms, 3)
     cpu = None
     if not a.no_cpu:
-        # targets in a 3.6 x 3.6 deg box at the field centre
+        # the sight lines in a 10 x 10 deg box at the field centre (1/9 of them),
+        # in latitude bands
         tl, tb = np.asarray(wl.target["lon"]), np.asarray(wl.target["lat"])
-        sel = np.nonzero((np.abs(tl - 120.0) < 1.8) & (np.abs(tb - 30.0) < 1.8))[0]
-        cpu, errs = cpu_baseline(wl, sel, "sight lines in a 3.6x3.6 deg box at (120, 30)", cubes)
-        extra["e_val"] = errs
+        sel = np.nonzero((np.abs(tl - 120.0) < 5.0) & (np.abs(tb - 30.0) < 5.0))[0]
+        job = oracle_job(wl, sel, cubes, wmaps, tsort=lambda l, b: b)
+        del cubes, wmaps
+        cpu, errs = cpu_baseline([job], "the sight lines in a 10x10 deg box at (120, 30)")
+        del job
+        extra.update(errs)
     out = base_line(a, ("sight lines: 10,000,000 samples x 256 BF16 channels over 30x30 deg -> "
                         "2,000,000 targets, gauss2d 3'x2' PA 30, support 9', nside 4096"),
                     contributions / (ms / 1e3), ms, "bf16",
@@ -516,20 +640,57 @@ def run_batched(a, dev):
     extra = {"eager": {"value": contributions / (ms_eager / 1e3), "ms_per_step": round(ms_eager, 4)},
              "tuned": {"rows_per_workgroup": b.query(5), "half_items": b.query(6),
                        "workgroups_per_cu": b.query(7), "shape": b.query(9), "items": b.query(3)}}
+    # the same 64 jobs through 64 separate FP32 gridders, one eager call each
+    outs32 = []
+    if not a.no_compare:
+        g32 = []
+        for wl in wls:
+            g = make_gridder(wl, dev)
+            g.set_precision("fp32")
+            g32.append(g)
+            nx, ny = wl.target["wcs"]["naxis1"], wl.target["wcs"]["naxis2"]
+            outs32.append((torch.empty((wl.nchan, ny, nx), dtype=torch.float32, device=dev),
+                           torch.empty((ny, nx), dtype=torch.float32, device=dev)))
+
+        def pass32():
+            for g, (lon, lat, d), (c, w) in zip(g32, ins, outs32):
+                g.grid_datacube(lon, lat, d, c, w)
+
+        pass32()
+        torch.cuda.synchronize()
+        for g in g32:
+            g.profile(True)
+        st32 = max(2, a.steps // 2)
+        t1 = time.perf_counter()
+        for _ in range(st32):
+            pass32()
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t1) * 1e3 / st32
+        k32 = sum(g.profile_read()[1] for g in g32) / st32
+        for g in g32:
+            g.profile(False)
+        log(f"batched fp32 (64 gridders): {ms32:.3f} ms/pass, contraction kernels {k32:.3f} ms")
+        extra["fp32_path"] = {"value": contributions / (ms32 / 1e3), "ms_per_step": round(ms32, 4),
+                              "kernel_ms": round(k32, 4),
+                              "how": "64 separate FP32 gridders, one eager call per job"}
+        extra["speedup_vs_fp32"] = round(ms32 / ms, 3)
     cpu = None
     if not a.no_cpu:
-        # the largest job's central 64x64 targets
-        j = int(np.argmax([wl.nsamples for wl in wls]))
-        wl = wls[j]
-        nx = wl.target["wcs"]["naxis1"]
-        ny = wl.target["wcs"]["naxis2"]
-        k = min(64, nx, ny)
-        x0, y0 = (nx - k) // 2, (ny - k) // 2
-        xs, ys = np.meshgrid(np.arange(x0, x0 + k), np.arange(y0, y0 + k))
-        cpu, errs = cpu_baseline(wl, (ys * nx + xs).ravel(),
-                                 f"job {j} (the largest): central {k}x{k} targets",
-                                 {"bf16": outs[j][0]})
-        extra["e_val"] = errs
+        # every job: its central band of rows (a quarter of the grid, full
+        # width, so both side edges are in)
+        jobs = []
+        for j, wl in enumerate(wls):
+            nx, ny = wl.target["wcs"]["naxis1"], wl.target["wcs"]["naxis2"]
+            y0, y1 = (3 * ny) // 8, max((5 * ny) // 8, (3 * ny) // 8 + 1)
+            tidx = np.arange(y0 * nx, y1 * nx)
+            cubes = {"bf16": outs[j][0]}
+            wmaps = {"bf16": outs[j][1]}
+            if outs32:
+                cubes["fp32"], wmaps["fp32"] = outs32[j]
+            jobs.append(oracle_job(wl, tidx, cubes, wmaps))
+        cpu, errs = cpu_baseline(jobs, "all 64 jobs, the central quarter of each grid's rows")
+        del jobs
+        extra.update(errs)
     out = base_line(a, ("batched: 64 jobs, 5k-500k samples, 64^2-512^2 SIN grids, 16-2048 BF16 "
                         "channels, 25% elliptical; one lookup pass + one persistent launch, "
                         "graph replay"),
@@ -541,13 +702,34 @@ def run_batched(a, dev):
     return out
 
 
+COMMON_KEYS = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")
+
+
+def run_all(a, dev):
+    """The cube line, with the batched jobs and the sight lines as objects of
+    it (each with its own value, roofline, cpu_baseline and e_val)."""
+    import torch
+    out = run_cube(a, dev)
+    subs = {}
+    for name, fn in (("batched", run_batched), ("sightlines", run_sightlines)):
+        _GRIDDERS.clear()
+        torch.cuda.empty_cache()
+        sub = fn(a, dev)
+        subs[name] = {k: v for k, v in sub.items() if k not in COMMON_KEYS}
+    _GRIDDERS.clear()
+    out["workloads"] = subs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube",
-                    choices=["cube", "allsky", "batched", "sightlines", "healpix", "map"])
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "cube", "allsky", "batched", "sightlines", "healpix", "map"],
+                    help="'all' (default): the cube as the headline line, with the batched "
+                         "jobs and the sight lines as objects of the same line")
     ap.add_argument("--prec", default="auto", choices=["auto", "fp32", "bf16", "fp16"],
                     help="contraction of the cube workload")
     ap.add_argument("--lookup", default="tiles", choices=["tiles", "disk"],
@@ -555,7 +737,8 @@ def main():
                          "query disks shifted along rings (Sect. 3.3)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
-    ap.add_argument("--cpu-block", type=int, default=384)
+    ap.add_argument("--cpu-block", type=int, default=0,
+                    help="cube workload: oracle on the central NxN targets (0: all of them)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -578,10 +761,14 @@ def main():
 
     global LOOKUP
     LOOKUP = a.lookup
-    if a.lookup != "tiles" and a.workload == "batched":
+    if a.lookup != "tiles" and a.workload in ("batched", "all"):
         print("batches always use the tile lookup", file=sys.stderr)
         sys.exit(2)
     dev = "cuda:0"
+    if a.workload == "all":
+        out = run_all(a, dev)
+        print(json.dumps(out), flush=True)
+        return
     run = {"cube": run_cube, "allsky": run_allsky, "batched": run_batched,
            "sightlines": run_sightlines, "healpix": run_healpix, "map": run_map}[a.workload]
     out = run(a, dev)

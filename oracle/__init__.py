@@ -38,4 +38,4 @@ from .wcs import wcs_world, wcs_targets  # noqa: F401
 from .healpix import ring_centres, nest_centres  # noqa: F401
 from .grid import (grid_bruteforce, grid_kdtree, kernel_weight,  # noqa: F401
                    neighbour_sets, grid_workload, targets_of)
-from .metrics import e_val, e_weights, pointwise_rel  # noqa: F401
+from .metrics import e_val, e_val_parts, e_val_combine, e_weights, pointwise_rel  # noqa: F401

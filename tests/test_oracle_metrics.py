@@ -112,13 +112,14 @@ def test_package_exports_the_pinned_functions():
 
 
 MUTATIONS = {
-    "norm_over_all_channels": ("norm = np.abs(R[:, m]).max(axis=1)\n",
-                               "norm = np.abs(R[:, m]).max()\n"),
-    "diff_over_channels_axis": ("diff = np.abs(R_hat[:, m] - R[:, m]).max(axis=1)",
-                                "diff = np.abs(R_hat[:, m] - R[:, m]).mean(axis=1)"),
-    "norm_from_tested": ("norm = np.abs(R[:, m]).max(axis=1)\n",
-                         "norm = np.abs(R_hat[:, m]).max(axis=1)\n"),
-    "mask_inverted": ("    m = _mask(W)\n    if cols", "    m = ~_mask(W)\n    if cols"),
+    "norm_over_all_channels": ("np.abs(R[:, m]).max(axis=1)\n",
+                               "np.full(C, np.abs(R[:, m]).max())\n"),
+    "diff_over_channels_axis": ("return np.abs(R_hat[:, m] - R[:, m]).max(axis=1)",
+                                "return np.abs(R_hat[:, m] - R[:, m]).mean(axis=1)"),
+    "norm_from_tested": ("np.abs(R[:, m]).max(axis=1)\n",
+                         "np.abs(R_hat[:, m]).max(axis=1)\n"),
+    "mask_inverted": ("    m = _mask(W)\n    if not np.array_equal",
+                      "    m = ~_mask(W)\n    if not np.array_equal"),
     "mask_all_false": ("return np.asarray(W, dtype=np.float64) > 0",
                        "return np.asarray(W, dtype=np.float64) > np.inf"),
     "no_empty_check": ("if not np.all(np.isnan(R_hat[:, ~m])):", "if False:"),
@@ -152,6 +153,28 @@ def test_planted_metric_mistakes_fail_a_pin(name):
     assert not _all_pins_pass(mutated(om, old, new)), f"planted mistake {name} passed every pin"
 
 
+def test_e_val_from_parts_of_blocks():
+    """The pieces of disjoint blocks combine to e_val of the union (used to
+    compare whole cubes block by block), including empty blocks and a zero
+    channel."""
+    g = np.random.default_rng(3)
+    R = g.normal(size=(4, 300))
+    R[2] = 0.0
+    W = g.uniform(0.5, 2.0, 300)
+    W[[5, 77, 250]] = 0.0
+    R[:, W == 0] = np.nan
+    Rh = R + g.normal(scale=1e-4, size=R.shape)
+    Rh[:, W == 0] = np.nan
+    whole = om.e_val(Rh, R, W)
+    cuts = [0, 7, 7, 120, 299, 300]
+    parts = [om.e_val_parts(Rh[:, a:b], R[:, a:b], W[a:b]) for a, b in zip(cuts[:-1], cuts[1:])]
+    assert om.e_val_combine(parts) == whole
+    with pytest.raises(AssertionError):
+        Rbad = Rh.copy()
+        Rbad[1, 3] = np.nan
+        om.e_val_parts(Rbad, R, W)
+
+
 # ---------------------------------------------------------- grid_kdtree(targets=)
 
 def test_kdtree_target_subset_equals_full_run():
@@ -180,3 +203,97 @@ def test_kdtree_target_subset_equals_full_run():
     brute = og.grid_bruteforce(lon, lat, x, tl[sub], tb[sub], kern, 9 / 60)
     np.testing.assert_array_equal(brute["count"], full["count"][sub])
     np.testing.assert_allclose(brute["W"], full["W"][sub], rtol=1e-12)
+
+
+# ------------------------------------------- targets_of / grid_workload glue
+
+def _glue_workloads():
+    import synth
+    from oracle import healpix as oh
+    g = np.random.default_rng(12)
+    out = []
+    # CAR at CRVAL2 = 0: pixel (x, y) centre is (CRVAL1 + CDELT1 (x + 1 - CRPIX1),
+    # CDELT2 (y + 1 - CRPIX2)), row-major with x fastest
+    wcs = synth.wcs_car(7, 5, 4.0, 3.0, 10.0, -0.5, 0.5)
+    xs, ys = np.meshgrid(np.arange(7), np.arange(5))
+    hand = ((10.0 - 0.5 * (xs + 1 - 4.0)).ravel(), (0.5 * (ys + 1 - 3.0)).ravel())
+    lon = g.uniform(8.0, 12.5, 2500)
+    lat = g.uniform(-1.5, 1.5, 2500)
+    out.append((synth.Workload("car", lon, lat, g.normal(size=(2500, 2)), "f64",
+                               {"kind": "wcs", "wcs": wcs}, ("gauss1d", (0.3,)), 0.9), hand))
+    lon, lat = synth.uniform_sphere(g, 3000)
+    for order in ("ring", "nested"):
+        out.append((synth.Workload(f"hpx {order}", lon, lat, g.normal(size=(3000, 1)), "f64",
+                                   {"kind": "healpix", "nside": 2, "order": order},
+                                   ("gauss1d", (8.0,)), 24.0),
+                    oh.centres(2, order)))
+    tl, tb = g.uniform(40, 42, 30), g.uniform(-5, -3, 30)
+    lon, lat = g.uniform(39.5, 42.5, 2000), g.uniform(-5.5, -2.5, 2000)
+    out.append((synth.Workload("sl", lon, lat, g.normal(size=(2000, 3)), "f64",
+                               {"kind": "sightlines", "lon": tl, "lat": tb},
+                               ("gauss2d", (0.2, 0.1, 30.0)), 0.6), (tl, tb)))
+    return out
+
+
+def test_grid_workload_grids_onto_the_described_targets():
+    """grid_workload (both methods, and with a target subset) equals brute
+    force onto targets worked out independently of targets_of."""
+    wls = _glue_workloads()
+    ring, nest = wls[1][1], wls[2][1]
+    assert not np.allclose(ring[0], nest[0])          # the order is honoured
+    for wl, (tl, tb) in wls:
+        ref = og.grid_bruteforce(wl.lon, wl.lat, wl.data, tl, tb, wl.kernel, wl.support)
+        assert ref["count"].sum() > 0
+        for res in (og.grid_workload(wl), og.grid_workload(wl, method="brute")):
+            np.testing.assert_array_equal(res["count"], ref["count"])
+            np.testing.assert_allclose(res["W"], ref["W"], rtol=1e-12, atol=1e-300)
+            m = ref["W"] > 0
+            np.testing.assert_allclose(res["R"][:, m], ref["R"][:, m], rtol=1e-10, atol=1e-12)
+        sub = np.arange(0, len(tl), 3)
+        part = og.grid_workload(wl, targets=sub)
+        np.testing.assert_array_equal(part["count"][sub], ref["count"][sub])
+        other = np.setdiff1d(np.arange(len(tl)), sub)
+        assert np.all(part["count"][other] == 0)
+
+
+GLUE_MUTATIONS = {
+    "lon_lat_swapped": ("    tlon, tlat = targets_of(wl)\n", "    tlat, tlon = targets_of(wl)\n"),
+    "order_ignored": ('healpix_centres(t["nside"], t.get("order", "ring"))',
+                      'healpix_centres(t["nside"], "ring")'),
+    "subset_ignored": ("                       targets=targets)", "                       targets=None)"),
+    "brute_gets_kdtree": ('if method == "brute":', 'if method == "never":'),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GLUE_MUTATIONS))
+def test_planted_glue_mistakes_fail_the_pin(name):
+    old, new = GLUE_MUTATIONS[name]
+    bad = mutated(og, old, new)
+    if name == "brute_gets_kdtree":
+        # both methods give the same numbers, so the plant is seen in the
+        # call it makes: brute force must not build a tree
+        import scipy.spatial
+        real = scipy.spatial.cKDTree
+        try:
+            def refuse(*a, **k):
+                raise AssertionError("tree built")
+            scipy.spatial.cKDTree = refuse
+            wl = _glue_workloads()[0][0]
+            og.grid_workload(wl, method="brute")
+            with pytest.raises(AssertionError):
+                bad.grid_workload(wl, method="brute")
+        finally:
+            scipy.spatial.cKDTree = real
+        return
+    with pytest.raises(AssertionError):
+        _check_glue(bad)
+
+
+def _check_glue(mod):
+    for wl, (tl, tb) in _glue_workloads():
+        ref = og.grid_bruteforce(wl.lon, wl.lat, wl.data, tl, tb, wl.kernel, wl.support)
+        res = mod.grid_workload(wl)
+        np.testing.assert_array_equal(res["count"], ref["count"])
+        sub = np.arange(0, len(tl), 3)
+        other = np.setdiff1d(np.arange(len(tl)), sub)
+        assert np.all(mod.grid_workload(wl, targets=sub)["count"][other] == 0)
