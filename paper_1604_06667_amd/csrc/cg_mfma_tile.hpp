@@ -134,7 +134,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   __shared__ double s_red[2][NW][kTile];
   __shared__ double s_wfin[2][kTile];
   __shared__ double s_tg[kTile][3];                    // target unit vectors
-  __shared__ float s_ax[(KT == 1 || KT == 2) ? kTile : 1][3];   // major axis at the target (elliptical)
+  __shared__ double s_ax[(KT == 1 || KT == 2) ? kTile : 1][3];  // major axis at the target (elliptical)
   __shared__ uint32_t s_pos[kListCands];               // sorted positions of the tile's candidates
   __shared__ uint32_t s_rb[kListRanges], s_rs[kListRanges];
 
@@ -175,7 +175,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
         a[2] = kp.cospa * nz;
       }
 #pragma unroll
-      for (int q = 0; q < 3; ++q) s_ax[t][q] = (float)a[q];
+      for (int q = 0; q < 3; ++q) s_ax[t][q] = a[q];
     }
   }
   // this thread's target in the weight block and its candidates kg, kg + NW, ...
@@ -221,10 +221,12 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   }
 
   // candidate record of chunk ch for thread t < MK (NaN / zero row past the
-  // end)
+  // end).  The record stays raw in registers until it is published one
+  // chunk later, so that nothing waits for its load in the meantime.
   const int64_t zoff = (int64_t)(zrow - data) - c0;   // offset that lands on the zero row
   double rx = nan, ry = nan, rz = nan;
-  int64_t rrow = zoff;
+  int64_t rrow = 0;       // input row of the record (valid when rok)
+  bool rok = false;
   // Odd tile rows of a WCS grid walk their candidates backwards (bottom ring
   // first): a tile and the one below it then reach the rings they share at
   // the same time, while those samples are in L2.
@@ -233,7 +235,7 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
   if (wv == 0 && !listed) rwin.init(rng, nr, total, !rev);
   auto load_rec = [&](int64_t ch) {   // every lane of wavefront 0
     rx = ry = rz = nan;
-    rrow = zoff;   // + channel offsets below stays inside the zero row
+    rok = false;   // the zero row: + channel offsets stays inside it
     if (ch < nchunks) {
       const uint32_t i0 = (uint32_t)ch * MK;
       const uint32_t cnt = total - i0 < (uint32_t)MK ? total - i0 : (uint32_t)MK;
@@ -252,7 +254,8 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
         rx = r.x;
         ry = r.y;
         rz = r.z;
-        rrow = rec_row(r) * ld;
+        rrow = rec_row(r);
+        rok = true;
       }
     }
   };
@@ -260,24 +263,30 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     s_c[buf][t][0] = rx;
     s_c[buf][t][1] = ry;
     s_c[buf][t][2] = rz;
-    s_row[buf][t] = rrow;
+    s_row[buf][t] = rok ? rrow * ld : zoff;
   };
   // weight of candidate k of the chunk in record buffer rb -> weight buffer wb
-  // Kernel value of a pair.  The support test is FP64 on the chord; the
-  // value itself only needs FP32 accuracy (it is rounded to 16-bit operand
-  // parts), so the distance series, the elliptical form and the exponential
-  // are evaluated in FP32 and masked by the test.
+  // Kernel value of a pair.  The support test is FP64 on the chord.  The
+  // value is rounded to 16-bit operand parts, but the weight map sums it
+  // unrounded, so it is held to about 2e-7 relative: the base-2 exponent's
+  // leading term (k c^2 for the circular Gaussian, kmin c^2 + (kmaj - kmin)
+  // u^2 for the elliptical one) is formed in FP64, its integer part split
+  // off exactly, and only the fraction, the small series corrections and
+  // the exponential are FP32.
   //
   // Elliptical kernel: with u, v the components of the chord along the
   // major and minor axes at the target (both tangent there), u^2 + v^2 is
   // the chord's tangential part c^2 (1 - c^2/4) exactly, so the exponent
   //   d^2 (u^2 kmaj + v^2 kmin) / (u^2 + v^2)
   // equals d^2 kmin + (kmaj - kmin) u^2 rq with rq = d^2 / (c^2 (1 - c^2/4)),
-  // which needs only u.  Supports below ~0.57 deg (c^2 <= 1e-4, uniform over
-  // the launch) take the two leading terms of d^2 = c^2 (1 + c^2/12 + ...)
-  // and rq = 1 + c^2/3 + ..., whose next terms are below 1e-8 relative.
+  // which needs only u.  With d^2 = c^2 (1 + s), s = c^2/12 + c^4/90 + ...,
+  // and rq = 1 + (s + c^2/4) / (1 - c^2/4), the exponent is the leading term
+  // plus kmin c^2 s + (kmaj - kmin) u^2 (rq - 1).  Supports below ~0.57 deg
+  // (c^2 <= 1e-4, uniform over the launch) keep s = c^2/12 and rq - 1 =
+  // c^2/3, whose next terms are below 1e-8 relative.
   const float k1f = (float)kp.k1, kminf = (float)kp.kmin, kdf = (float)(kp.kmaj - kp.kmin);
   const float ksf = (float)kp.ks, tinvf = (float)kp.tinv;
+  const double kdd = kp.kmaj - kp.kmin;
   const bool short_support = kp.cs2 <= 1e-4;
   auto weight = [&](int rb, int wb, int k) {
     const double dx = s_c[rb][k][0] - s_tg[nw][0];
@@ -285,33 +294,23 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
     const double dz = s_c[rb][k][2] - s_tg[nw][2];
     const double c2 = dx * dx + dy * dy + dz * dz;
     const float c = (float)c2;
-    float d2, rq;
-    if (short_support) {
-      d2 = c + c * c * (1.0f / 12.0f);
-      rq = 1.0f + c * (1.0f / 3.0f);
-    } else {
-      d2 = c * (1.0f + c * (1.0f / 12.0f + c * (1.0f / 90.0f + c * (1.0f / 560.0f +
-               c * (1.0f / 3150.0f + c * (1.0f / 16632.0f))))));
-      if (c2 > 0.1225) d2 = (float)chord2_to_d2_exact(c2);   // chords beyond ~20 deg
-      const float uv = c * (1.0f - 0.25f * c);
-      rq = uv > 0.0f ? d2 * __builtin_amdgcn_rcpf(uv) : 1.0f;
-    }
-    float x = d2 * k1f;
-    if constexpr (KT == 1 || KT == 2) {
-      if (ell) {
-        const float u = (float)dx * s_ax[nw][0] + (float)dy * s_ax[nw][1] + (float)dz * s_ax[nw][2];
-        x = d2 * kminf + kdf * (u * u) * rq;
-      }
-    }
+    // s = d^2 / c^2 - 1 (series, or exact for chords beyond ~20 deg)
+    auto series = [&]() -> float {
+      if (short_support) return c * (1.0f / 12.0f);
+      if (c2 > 0.1225) return (float)(chord2_to_d2_exact(c2) / c2 - 1.0);
+      return c * (1.0f / 12.0f + c * (1.0f / 90.0f + c * (1.0f / 560.0f +
+             c * (1.0f / 3150.0f + c * (1.0f / 16632.0f)))));
+    };
     float w;
     if constexpr (KT == 3) {
       // radial kernels of arbitrary shape: the tapered sinc, or the
       // tabulated profile interpolated linearly (zero past its last point)
+      const float d2 = c * (1.0f + series());
       const float d = sqrtf(d2);
       float v;
       if (kp.type == 2) {
         const float a = ksf * d;
-        v = __builtin_amdgcn_exp2f(-x) * (a > 0.0f ? sinf(a) / a : 1.0f);
+        v = __builtin_amdgcn_exp2f(-(d2 * k1f)) * (a > 0.0f ? sinf(a) / a : 1.0f);
       } else {
         const float u = d * tinvf;
         const int last = kp.ntab - 1;
@@ -326,7 +325,27 @@ __device__ __forceinline__ void mfma_tile(const TileView tv, const KernelParams 
       }
       w = c2 <= kp.cs2 ? v : 0.0f;
     } else {
-      w = c2 <= kp.cs2 ? __builtin_amdgcn_exp2f(-x) : 0.0f;
+      const float sr = series();
+      double xl = c2 * kp.k1;        // leading term of the exponent
+      float corr = (float)xl * sr;   // the rest
+      if constexpr (KT == 1 || KT == 2) {
+        if (ell) {
+          const double u = dx * s_ax[nw][0] + dy * s_ax[nw][1] + dz * s_ax[nw][2];
+          const double u2 = u * u;
+          const float den = 1.0f - 0.25f * c;   // zero only for an antipodal sample (u = 0)
+          const float rq1 = short_support ? c * (1.0f / 3.0f)
+                            : den > 0.0f ? (sr + 0.25f * c) * __builtin_amdgcn_rcpf(den) : 0.0f;
+          xl = fma(kdd, u2, c2 * kp.kmin);
+          corr = kminf * c * sr + kdf * (float)u2 * rq1;
+        }
+      }
+      // 2^-(xl + corr) with the integer part of xl split off exactly, so
+      // that rounding to FP32 costs < 6e-8 absolute in the exponent however
+      // far out the sample is (exponents reach ~26 at the edge of a 3-sigma
+      // support along the minor axis of a 2:1 ellipse)
+      const double fl = floor(xl);
+      const float v = ldexpf(__builtin_amdgcn_exp2f(-((float)(xl - fl) + corr)), (int)(-fl));
+      w = c2 <= kp.cs2 ? v : 0.0f;
     }
     const uint16_t whi = to_bits<F16>(w);
     float wr = from_bits<F16>(whi);

@@ -9,8 +9,8 @@ benchmark times, on sampled outputs the FP64 oracle computes one by one.
   cube): BF16, FP16 and FP32 paths on the targets of a 0.8x0.8 deg box;
 * HEALPix map (App. A.1: ~47 M samples x 2 -> the nside = 512 pixel
   centres): FP32 path at both poles and across the seam;
-* batched (64 uneven jobs, tuned, replayed from the captured graph): the
-  three largest jobs on central blocks;
+* batched (64 uneven jobs, tuned, replayed from the captured graph): every
+  job on a central and an edge block, with neighbour counts;
 * the sample-centric lookup (query disks shifted with Eq. 4-5) on the cube
   and the sight lines: neighbour counts and hashes identical to the tile
   lookup's at every target, and the BF16 path on the sampled blocks.
@@ -213,6 +213,11 @@ def test_fullsize_healpix_map():
 
 
 def test_fullsize_batched_graph():
+    """Every one of the 64 jobs, replayed from the captured graph after
+    tuning: a central 16 x 16 block and a 16 x 16 block at the grid's edge
+    against the oracle (e_val, e_W) and the neighbour counts of both blocks
+    (from the job's own lookup) against the oracle's; the elliptical jobs
+    are among them."""
     torch = _torch()
     import paper_1604_06667_amd as cgp
     wls = synth.config4(device="cuda:0")
@@ -224,13 +229,24 @@ def test_fullsize_batched_graph():
     b.capture(ins, outs)
     for c, w in outs:
         c.fill_(-7.0)
+        w.fill_(-7.0)
     b.replay()
     b.sync()
-    for j in np.argsort([-wl.nsamples for wl in wls])[:3]:
-        wl = wls[j]
+    nell = 0
+    worst = (0.0, 0.0)
+    for j, wl in enumerate(wls):
         nx, ny = wl.target["wcs"]["naxis1"], wl.target["wcs"]["naxis2"]
-        tidx = _blocks(nx, ny, [(ny // 2 - 10, nx // 2 - 10)], 20)
+        k = min(16, nx, ny)
+        tidx = _blocks(nx, ny, [(ny // 2 - k // 2, nx // 2 - k // 2), (ny - k, 0)], k)
         ref, sidx = _oracle_on(wl, tidx)
+        counts, _ = gs[j].neighbour_stats(*ins[j][:2])
+        _check_counts(wl, counts, tidx, ref, sidx)
         ev = _ev(outs[j][0], wl, tidx, ref)
-        say(f"  job {j} (N={wl.nsamples}, C={wl.nchan}, {wl.kernel[0]}) e_val={ev:.2e}")
-        assert ev <= TOL_MFMA
+        ew = oracle.e_weights(outs[j][1].reshape(-1)[torch.as_tensor(tidx, device="cuda:0")]
+                              .cpu().numpy(), ref["W"])
+        nell += wl.kernel[0] == "gauss2d"
+        worst = (max(worst[0], ev), max(worst[1], ew))
+        say(f"  job {j} (N={wl.nsamples}, C={wl.nchan}, {wl.kernel[0]}) e_val={ev:.2e} e_W={ew:.2e}")
+        assert ev <= TOL_MFMA and ew <= TOL32
+    say(f"  64 jobs ({nell} elliptical): worst e_val={worst[0]:.2e} e_W={worst[1]:.2e}")
+    assert nell > 0
