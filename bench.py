@@ -56,6 +56,7 @@ METRIC = ("gridded sample-channel contributions/sec on 1 GPU, BF16-MFMA vs FP32 
           "≤2e-3 rel")
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6   # FP32 (packed FP32 disabled) and FP64: 256 CU x 64 lanes x 2 x 2.4 GHz
+PEAK_PACKED_FP32_TFLOPS = 157.3   # FP32 with packed instructions (not used by these builds)
 PEAK_BF16_TFLOPS = 2500.0
 FLOPS_PER_PAIR = 12       # FP64 chord^2, support test, distance series per in-support pair
 
@@ -99,33 +100,74 @@ def traffic_from_profiles(kernel_tag):
 
 def roof_hbm(alg_bytes, kms, tag):
     ach = alg_bytes / (kms * 1e-3) / 1e9
+    bw = copy_bandwidth()
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic_from_profiles(tag),
-            "kernel_ms": round(kms, 4), "alg_bytes": int(alg_bytes)}
+            "kernel_ms": round(kms, 4), "alg_bytes": int(alg_bytes),
+            "copy_bw_measured": round(bw, 1), "frac_of_measured_copy_bw": round(ach / bw, 4)}
 
 
 def roof_alu(flops, kms, tag):
     ach = flops / (kms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_VALU_TFLOPS, 4),
+            "frac_of_packed_fp32_peak": round(ach / PEAK_PACKED_FP32_TFLOPS, 4),
             "traffic": traffic_from_profiles(tag), "kernel_ms": round(kms, 4),
             "alg_flops": float(flops)}
 
 
-def time_path(g, lon, lat, data, cube, weights, steps, warmup):
+STEP_MS = {}   # per-step HIP-event times of the last timed loop, by label
+
+
+def timed_steps(fn, steps, label):
+    """Run fn() steps times between two host synchronisations; returns the
+    mean wall time per step (ms) and records each step's HIP-event time
+    (events on the current stream, which the library's calls use)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    STEP_MS[label] = {"median": round(per[len(per) // 2], 4), "min": round(per[0], 4)}
+    return (t1 - t0) * 1e3 / steps
+
+
+def time_path(g, lon, lat, data, cube, weights, steps, warmup, label="step"):
     import torch
     for _ in range(warmup):
         g.grid_datacube(lon, lat, data, cube, weights)
     torch.cuda.synchronize()
     g.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        g.grid_datacube(lon, lat, data, cube, weights)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms = timed_steps(lambda: g.grid_datacube(lon, lat, data, cube, weights), steps, label)
     g.profile(False)
     nl, kms = g.profile_read()
-    return (t1 - t0) * 1e3 / steps, (kms / max(nl, 1)), nl
+    return ms, (kms / max(nl, 1)), nl
+
+
+_COPY_BW = None
+
+
+def copy_bandwidth():
+    """Device copy bandwidth measured in this run: a 2 GiB buffer copied 10
+    times; GB/s counts bytes read plus bytes written."""
+    global _COPY_BW
+    if _COPY_BW is None:
+        import torch
+        src = torch.ones(1 << 29, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        ms = timed_steps(lambda: dst.copy_(src), 10, "copy")
+        _COPY_BW = 2.0 * src.numel() * 4 / (ms * 1e-3) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+    return _COPY_BW
 
 
 # ------------------------------------------------------------ CPU baseline
@@ -332,10 +374,13 @@ def count_contributions(g, lon, lat, nchan):
     return pairs, pairs * nchan
 
 
-def base_line(a, wl_desc, value, ms, dtype, config, roof, cpu):
+def base_line(a, wl_desc, value, ms, dtype, config, roof, cpu, step_label="step"):
+    import torch
     if LOOKUP != "tiles":
         config = dict(config, lookup=LOOKUP)
     return {"metric": METRIC, "value": value, "unit": "contributions/s",
+            "step_ms_events": STEP_MS.get(step_label), "rocm": torch.version.hip,
+            "clocks": "default (not pinned)",
             "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": dtype, "data": "synthetic",
@@ -370,13 +415,14 @@ def run_cube(a, dev):
     g.set_precision(headline)
     cube = torch.empty((wl.nchan, 600, 600), dtype=torch.float32, device=dev)
     weights = torch.empty((600, 600), dtype=torch.float32, device=dev)
-    ms, kms, nl = time_path(g, lon, lat, data, cube, weights, a.steps, a.warmup)
+    ms, kms, nl = time_path(g, lon, lat, data, cube, weights, a.steps, a.warmup, label="cube")
     log(f"{headline}: {ms:.3f} ms/step, contraction kernel {kms:.3f} ms x {nl}")
     cubes, wmaps = {headline: cube.clone()}, {headline: weights.clone()}
     extra = {}
     if headline != "fp32" and not a.no_compare:
         g.set_precision("fp32")
-        ms32, kms32, _ = time_path(g, lon, lat, data, cube, weights, max(2, a.steps // 2), 1)
+        ms32, kms32, _ = time_path(g, lon, lat, data, cube, weights, max(2, a.steps // 2), 1,
+                                   label="cube_fp32")
         cubes["fp32"], wmaps["fp32"] = cube.clone(), weights.clone()
         extra["fp32_path"] = {"value": contributions / (ms32 / 1e3), "ms_per_step": round(ms32, 4),
                               "kernel_ms": round(kms32, 4)}
@@ -403,7 +449,7 @@ def run_cube(a, dev):
                     contributions / (ms / 1e3), ms, DT[headline],
                     {"samples": wl.nsamples, "targets": ntarget, "channels": wl.nchan,
                      "nside": g.nside, "pairs": pairs, "contributions": contributions,
-                     "contraction": headline}, roof, cpu)
+                     "contraction": headline}, roof, cpu, step_label="cube")
     out.update(extra)
     return out
 
@@ -463,13 +509,9 @@ def run_allsky(a, dev):
     roof["alg_bytes"] = int(wl.nsamples * (wl.nchan * 4 + 16) + nx * ny * (wl.nchan * 4 + 4))
     cpu, extra = None, {}
     if not a.no_cpu:
-        # a block of targets across the 0/360 seam on the equator
-        k = 768
-        y0, x0 = ny // 2 - k // 2, nx // 2 - k // 2
-        xs, ys = np.meshgrid(np.arange(x0, x0 + k), np.arange(y0, y0 + k))
-        cpu, errs = cpu_baseline([oracle_job(wl, (ys * nx + xs).ravel(), {"fp32": cube},
+        cpu, errs = cpu_baseline([oracle_job(wl, np.arange(nx * ny), {"fp32": cube},
                                              {"fp32": weights})],
-                                 f"{k}x{k} targets across the 0/360 seam on the equator")
+                                 f"all {nx}x{ny} targets (both poles, the 0/360 seam)")
         extra.update(errs)
     out = base_line(a, ("all-sky map: 12,000,000 uniform samples x 8 FP32 channels -> 4320x2160 "
                         "CAR at 5', gauss1d sigma 6', support 18', nside 1024"),
@@ -542,7 +584,8 @@ def run_sightlines(a, dev):
             continue
         g.set_precision(prec)
         st = a.steps if prec != "fp32" else max(2, a.steps // 2)
-        ms, kms, nl = time_path(g, lon, lat, data, cube, weights, st, 1 if prec == "fp32" else a.warmup)
+        ms, kms, nl = time_path(g, lon, lat, data, cube, weights, st, 1 if prec == "fp32" else a.warmup,
+                                label="sightlines_" + prec)
         res[prec] = (ms, kms)
         cubes[prec] = cube.t().contiguous()
         wmaps[prec] = weights.clone()
@@ -579,7 +622,8 @@ def run_sightlines(a, dev):
                     contributions / (ms / 1e3), ms, "bf16",
                     {"samples": wl.nsamples, "targets": nt, "channels": wl.nchan,
                      "nside": g.nside, "pairs": pairs, "contributions": contributions,
-                     "contraction": "bf16", "layout": "target-major [T][C]"}, roof, cpu)
+                     "contraction": "bf16", "layout": "target-major [T][C]"}, roof, cpu,
+                    step_label="sightlines_bf16")
     out.update(extra)
     return out
 
@@ -629,11 +673,7 @@ def run_batched(a, dev):
     for _ in range(a.warmup):
         b.replay()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(a.steps):
-        b.replay()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t1) * 1e3 / a.steps
+    ms = timed_steps(b.replay, a.steps, "batched")
     b.sync()
     log(f"batched: eager {ms_eager:.3f} ms/step (contraction {kms:.3f} ms), graph {ms:.3f} ms/step")
     roof = roof_hbm(alg_bytes, kms, "contraction_batched_bf16")
@@ -697,7 +737,8 @@ def run_batched(a, dev):
                     contributions / (ms / 1e3), ms, "bf16",
                     {"jobs": len(wls), "samples": int(sum(w.nsamples for w in wls)),
                      "targets": int(sum(w.ntargets() for w in wls)), "pairs": pairs,
-                     "contributions": contributions, "contraction": "bf16"}, roof, cpu)
+                     "contributions": contributions, "contraction": "bf16"}, roof, cpu,
+                    step_label="batched")
     out.update(extra)
     return out
 
