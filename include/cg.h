@@ -194,7 +194,8 @@ cg_status cg_create_healpix(cg_gridder** out, int64_t nside, int32_t order, int6
  * values finite; the table is copied into the handle, after the device has
  * finished earlier work).  The batch API takes
  * GAUSS1D and GAUSS2D gridders only.  support_deg: radius beyond which samples are ignored (0 <
- * support < 90).  hpx_maxres_deg: resolution of the internal HEALPix grid;
+ * support < 90, and at most 1000 times the Gaussian's sigma, sigma_min for
+ * GAUSS2D, the taper's sigma for TAPERED_SINC).  hpx_maxres_deg: resolution of the internal HEALPix grid;
  * nside = smallest power of two with sqrt(pi/3)/nside <= hpx_maxres (a
  * speed knob only: the support test is exact), unless cg_set_nside fixed
  * it.  Builds the handle's lookup tables for this support (the HEALPix

@@ -520,10 +520,12 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
   // every argument is checked before the handle changes, so a rejected call
   // leaves the previous kernel (and its table) in force
   cg::KernelParams kp{};
+  double smin = 0.0;   // narrowest Gaussian width (rad), 0 for a table
   if (kernel_type == CG_GAUSS1D) {
     if (nparams != 1) return fail(CG_E_INVALID, "gauss1d takes 1 parameter (sigma)");
     const double s = params[0] * kDeg;
     if (!(s > 0.0) || !isfinite(s)) return fail(CG_E_INVALID, "sigma must be > 0");
+    smin = s;
     kp.type = 0;
     kp.k1 = kLog2e / (2.0 * s * s);
   } else if (kernel_type == CG_GAUSS2D) {
@@ -532,6 +534,7 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
     if (!(a > 0.0 && b > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(pa))
       return fail(CG_E_INVALID, "sigmas must be > 0 and pa finite");
     if (b > a) return fail(CG_E_INVALID, "sigma_min must not exceed sigma_maj");
+    smin = b;
     kp.type = 1;
     kp.kmaj = kLog2e / (2.0 * a * a);
     kp.kmin = kLog2e / (2.0 * b * b);
@@ -542,6 +545,7 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
     const double s = params[0] * kDeg, b = params[1] * kDeg;
     if (!(s > 0.0 && b > 0.0) || !isfinite(s) || !isfinite(b))
       return fail(CG_E_INVALID, "sigma and b must be > 0");
+    smin = s;
     kp.type = 2;
     kp.k1 = kLog2e / (2.0 * s * s);
     kp.ks = cg::hpx::kPi / b;
@@ -561,6 +565,10 @@ cg_status cg_set_kernel(cg_gridder* g, int32_t kernel_type, const double* params
   if (!(support_deg > 0.0 && support_deg < 90.0))
     return fail(CG_E_INVALID, "support must be in (0, 90) degrees");
   const double rs = support_deg * kDeg;
+  // the base-2 exponent of a Gaussian weight inside the support then stays
+  // below 1000^2 / 2 * log2(e), about 7.2e5, so its integer part fits an int
+  if (smin > 0.0 && rs > 1000.0 * smin)
+    return fail(CG_E_INVALID, "support must not exceed 1000 sigma (sigma_min for gauss2d)");
   const double c = 2.0 * sin(0.5 * rs);
   kp.cs2 = c * c;
   int64_t nside = g->nside;

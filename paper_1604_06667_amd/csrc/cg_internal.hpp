@@ -225,10 +225,9 @@ __device__ __forceinline__ double chord2_to_d2(double c2) {
 // that rounding x to FP32 does not cost accuracy at large x.
 __device__ __forceinline__ float exp2_neg(double x) {
   const double xi = floor(x);
+  if (xi > 126.0) return 0.0f;   // before the conversion: no int overflow
   const float f = (float)(x - xi);
-  const int e = (int)xi;
-  if (e > 126) return 0.0f;
-  return ldexpf(exp2f(-f), -e);
+  return ldexpf(exp2f(-f), -(int)xi);
 }
 
 // Kernel weight for a pair with chord vector (dx, dy, dz) = p_n - p_t and

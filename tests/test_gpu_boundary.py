@@ -286,3 +286,24 @@ def test_accumulate_64_chunks(prec, tol):
     ew = oracle.e_weights(W, ref["W"])
     say(f"  64 chunks {prec}: e_val={ev:.3e} e_W={ew:.3e}")
     assert ev <= tol and ew <= TOL32
+
+
+@pytest.mark.gpu
+def test_support_beyond_1000_sigma_is_rejected():
+    """A support of more than 1000 sigma (sigma_min for the elliptical
+    kernel) is refused, and the kernel in force before stays usable."""
+    torch = _torch()
+    cgp = pytest.importorskip("paper_1604_06667_amd")
+    wl = synth.config_tiny_grid(9, 3)
+    g = make_gridder(wl, "fp32")
+    sig = wl.kernel[1][0]
+    with pytest.raises(cgp.CgError):
+        g.set_kernel("gauss1d", (sig,), 1001.0 * sig, wl.hpx_maxres or 0.5 * sig)
+    with pytest.raises(cgp.CgError):
+        g.set_kernel("gauss2d", (sig, sig / 2000.0, 30.0), 1.0 * sig, wl.hpx_maxres or 0.5 * sig)
+    lon, lat, d = to_device(wl)
+    c, w = g.grid_datacube(lon, lat, d)
+    torch.cuda.synchronize()
+    ref = oracle.grid_workload(wl)
+    R, W = _np(c, w, wl.nchan)
+    assert oracle.e_val(R, ref["R"], ref["W"]) <= TOL32
