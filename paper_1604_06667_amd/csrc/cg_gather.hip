@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(512) k_gather_cl(TileView tv, KernelParams kp,
         const double c2 = dx * dx + dy * dy + dz * dz;
         if (c2 <= kp.cs2) {
           if (KT == 0)
-            w = exp2_neg(chord2_to_d2(c2) * kp.k1);
+            w = exp2_neg(chord2_to_d2_for(kp, c2) * kp.k1);
           else
             w = pair_weight<KT == 3>(kp, c2, dx, dy, dz, s_t[tt][3], s_t[tt][4], s_t[tt][5], s_t[tt][6],
                             s_t[tt][7], s_t[tt][8]);
