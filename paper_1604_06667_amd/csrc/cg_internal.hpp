@@ -233,8 +233,9 @@ __device__ __forceinline__ double chord2_to_d2_for(const KernelParams& kp, doubl
 __device__ __forceinline__ float exp2_neg(double x) {
   const double xi = floor(x);
   if (xi > 126.0) return 0.0f;   // before the conversion: no int overflow
-  const float f = (float)(x - xi);
-  return ldexpf(exp2f(-f), -(int)xi);
+  // 2^-f for f in [0, 1) lies in (0.5, 1], where the hardware exp2 needs no
+  // range handling
+  return ldexpf(__builtin_amdgcn_exp2f(-(float)(x - xi)), (int)(-xi));
 }
 
 // Kernel weight for a pair with chord vector (dx, dy, dz) = p_n - p_t and
@@ -271,6 +272,12 @@ __device__ __forceinline__ float pair_weight(const KernelParams& kp, double c2, 
   if constexpr (RADIAL) return (float)radial_weight(kp, d2);
   if (kp.type == 0) return exp2_neg(d2 * kp.k1);
   const double u = dx * ax + dy * ay + dz * az;
+  if (kp.cs2 <= 1e-4) {
+    // u^2 + v^2 is the chord's tangential part c^2 (1 - c^2/4) exactly, so
+    // the exponent is d^2 kmin + (kmaj - kmin) u^2 d^2 / (c^2 (1 - c^2/4)),
+    // and for these supports d^2 / (c^2 (1 - c^2/4)) = 1 + c^2/3 to 1e-9
+    return exp2_neg(fma((kp.kmaj - kp.kmin) * u * u, fma(c2, 1.0 / 3.0, 1.0), d2 * kp.kmin));
+  }
   const double v = dx * bx + dy * by + dz * bz;
   const double uv = u * u + v * v;
   if (uv <= 0.0) return 1.0f;
