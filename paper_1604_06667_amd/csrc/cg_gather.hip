@@ -45,8 +45,8 @@ __device__ __forceinline__ float qnan_f() { return __int_as_float(0x7fc00000); }
 // first marks, in a 64-bit mask, the candidates within the support of its
 // target (FP64 test), then walks only its own marked candidates: weight and
 // channel products for those pairs alone, with no lane idling on the pairs
-// of other targets.  Sums per lane run in candidate order, as in the
-// definition.
+// of other targets.  Sums per lane run in the tile's visit order (see the
+// loop), the same on every call.
 
 template <int CMAX, bool RADIAL>
 __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
@@ -66,14 +66,45 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
   for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
   double wacc = 0.0;
   const uint32_t total = (uint32_t)tv.ntot[tile];
-  RangeWindow<false> rw;
-  rw.init(tv.rng + 2 * tv.roff[tile], tv.nr[tile], total, true);
+  const uint32_t nr = tv.nr[tile];
+  const uint32_t* rng = tv.rng + 2 * tv.roff[tile];   // per range: first sorted position, first candidate index
   const double thr = 1.0 - 0.5 * kp.cs2 - 2e-15;
-  for (uint32_t base = 0; base < total; base += kChunk) {
-    const int kmax = (int)(total - base < (uint32_t)kChunk ? total - base : (uint32_t)kChunk);
-    rw.cover(base, base + kmax - 1, true);
-    const int64_t pos = rw.pos(base + (lane < kmax ? lane : kmax - 1), base, base + kmax - 1);
-    if (lane < kmax) {
+  // Visit order.  The candidates are sorted ring by ring, and only the
+  // lanes whose target lies near a ring have pairs in its stretch, so a
+  // chunk of consecutive candidates would leave most lanes idle while a few
+  // walk their marked pairs.  The tile is therefore visited interleaved:
+  // chunk ci takes candidates ci, nch + ci, 2 nch + ci, ..., one from each
+  // 64th of the list, so every lane finds about its average share of pairs
+  // in every chunk.  Lane j loads the candidates of its 64th in order,
+  // following the ranges with a cursor of its own: it finds the range of
+  // its first candidate by a binary search and, ranges being non-empty,
+  // steps to the next range at most once per chunk.
+  const uint32_t nch = (total + kChunk - 1) / kChunk;
+  const uint64_t q0 = (uint64_t)lane * nch;
+  uint32_t rb = 0, rs = 0, re = 0, ri = 0;   // cursor: range ri = positions rb.. for candidates [rs, re)
+  if (q0 < total) {
+    uint32_t lo = 0, hi = nr - 1;   // last range whose first candidate index is <= q0
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (rng[2 * mid + 1] <= q0) lo = mid;
+      else hi = mid - 1;
+    }
+    ri = lo;
+    rb = rng[2 * ri];
+    rs = rng[2 * ri + 1];
+    re = ri + 1 < nr ? rng[2 * ri + 3] : total;
+  }
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  for (uint32_t ci = 0; ci < nch; ++ci) {
+    const uint64_t q = q0 + ci;
+    if (q < total) {
+      while (q >= re) {   // re < total here, so range ri + 1 exists
+        ++ri;
+        rb = rng[2 * ri];
+        rs = re;
+        re = ri + 1 < nr ? rng[2 * ri + 3] : total;
+      }
+      const int64_t pos = (int64_t)rb + (int64_t)(q - rs);
       const double4 r = tv.srec[pos];
       s_x[lane] = r.x;
       s_y[lane] = r.y;
@@ -81,6 +112,8 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
         if (c < nchan) s_d[lane * CMAX + c] = (double)sdata[pos * nchan + c];
+    } else {
+      s_x[lane] = s_y[lane] = s_z[lane] = nan;   // no candidate: no test marks it
     }
     __syncthreads();
     // candidates of the chunk that may lie within the support of this lane's
@@ -90,17 +123,10 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
     // rounding of the dot product, so the marked set is a superset.  The
     // exact FP64 chord test below decides every marked pair.
     uint64_t inside = 0;
-    if (kmax == kChunk) {
 #pragma unroll
-      for (int k = kChunk - 1; k >= 0; --k) {
-        const double dot = fma(s_x[k], tx, fma(s_y[k], ty, s_z[k] * tz));
-        inside = (inside << 1) | (uint64_t)(dot >= thr);
-      }
-    } else {
-      for (int k = kmax - 1; k >= 0; --k) {
-        const double dot = fma(s_x[k], tx, fma(s_y[k], ty, s_z[k] * tz));
-        inside = (inside << 1) | (uint64_t)(dot >= thr);
-      }
+    for (int k = kChunk - 1; k >= 0; --k) {
+      const double dot = fma(s_x[k], tx, fma(s_y[k], ty, s_z[k] * tz));
+      inside = (inside << 1) | (uint64_t)(dot >= thr);
     }
     while (inside) {
       const int k = __builtin_ctzll(inside);
