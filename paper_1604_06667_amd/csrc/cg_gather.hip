@@ -109,9 +109,11 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
       s_x[lane] = r.x;
       s_y[lane] = r.y;
       s_z[lane] = r.z;
+      // every slot of the row is written (zeros past nchan), so the walk
+      // reads and multiplies all CMAX slots without a branch per channel
 #pragma unroll
       for (int c = 0; c < CMAX; ++c)
-        if (c < nchan) s_d[lane * CMAX + c] = (double)sdata[pos * nchan + c];
+        s_d[lane * CMAX + c] = c < nchan ? (double)sdata[pos * nchan + c] : 0.0;
     } else {
       s_x[lane] = s_y[lane] = s_z[lane] = nan;   // no candidate: no test marks it
     }
@@ -138,8 +140,7 @@ __global__ void __launch_bounds__(64) k_gather_tl(TileView tv, KernelParams kp,
                                     : 0.0;
       wacc += w;
 #pragma unroll
-      for (int c = 0; c < CMAX; ++c)
-        if (c < nchan) acc[c] = fma(w, s_d[k * CMAX + c], acc[c]);
+      for (int c = 0; c < CMAX; ++c) acc[c] = fma(w, s_d[k * CMAX + c], acc[c]);
     }
     __syncthreads();
   }
