@@ -33,6 +33,7 @@ struct cg_batch {
   cg::BatchItem* pin_items = nullptr;
   size_t pin_items_cap = 0;
   int64_t nitems = 0;
+  cg::BatchQueues queues{};                  // the items' segment of each XCD
   bool items_valid = false;
   std::vector<int64_t> items_for_n;          // sample counts the queue was ordered for
   // tuned launch shape (cg::launch_batch_mfma), item width, workgroups per CU
@@ -111,8 +112,11 @@ double item_cost(const cg_gridder* g, int64_t n, int64_t cw) {
   return cand * (double)(cw + 64);
 }
 
-// (Re)build the work queue for the current launch shape and sample counts:
-// items of every job, jobs in order of decreasing estimated item cost.
+// (Re)build the work queues for the current launch shape and sample
+// counts: one segment per XCD, holding for every job (in order of
+// decreasing estimated item cost) the items of one run of its tiles.  A
+// WCS job's tiles are taken in the per-grid kernel's strip order, so each
+// XCD gets a compact patch of the grid, as a single grid call gives it.
 cg_status build_items(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
   const int njobs = (int)b->jobs.size();
   const int64_t cp = cg::batch_shape_rows(b->shape);
@@ -134,16 +138,23 @@ cg_status build_items(cg_batch* b, const cg_batch_job* in, hipStream_t st) {
                    [](const JobOrder& a, const JobOrder& c) { return a.cost > c.cost; });
   b->hitems.clear();
   b->hitems.reserve((size_t)total);
-  for (const JobOrder& o : ord) {
-    const cg_gridder* g = b->jobs[o.j];
-    for (int64_t t = 0; t < g->ntiles; ++t)
-      for (int64_t p = 0; p < o.npass; ++p) {
-        const int64_t c0 = p * o.cw;
-        const int64_t ce = std::min(c0 + o.cw, g->nchan);
-        b->hitems.push_back({o.j, (int32_t)t, (int32_t)c0, (int32_t)ce});
+  for (int k = 0; k < cg::kNumXcd; ++k) {
+    b->queues.off[k] = (int64_t)b->hitems.size();
+    for (const JobOrder& o : ord) {
+      const cg_gridder* g = b->jobs[o.j];
+      const int64_t v0 = g->ntiles * k / cg::kNumXcd, v1 = g->ntiles * (k + 1) / cg::kNumXcd;
+      for (int64_t v = v0; v < v1; ++v) {
+        const int64_t t = g->ntx > 0 ? cg::strip_tile(v, g->ntiles, g->ntx) : v;
+        for (int64_t p = 0; p < o.npass; ++p) {
+          const int64_t c0 = p * o.cw;
+          const int64_t ce = std::min(c0 + o.cw, g->nchan);
+          b->hitems.push_back({o.j, (int32_t)t, (int32_t)c0, (int32_t)ce});
+        }
       }
+    }
   }
   b->nitems = (int64_t)b->hitems.size();
+  b->queues.off[cg::kNumXcd] = b->nitems;
   const size_t bytes = sizeof(cg::BatchItem) * std::max<size_t>(1, b->hitems.size());
   cg_status s = grow(b, b->items, bytes, "alloc work items");
   if (s != CG_OK) return s;
@@ -274,7 +285,7 @@ const uint32_t* sorted_vals(const cg_batch* b) {
 // Device work after the lookup: the persistent contraction over the queue.
 cg_status contract_part(cg_batch* b, hipStream_t st, bool events) {
   const cg::BatchJob* dj = b->d_jobs.as<cg::BatchJob>();
-  CG_HIP(cg::launch_fill(b->counter.as<float>(), 1, 0.0f, st), "clear counter");
+  CG_HIP(cg::launch_fill(b->counter.as<float>(), cg::kNumXcd, 0.0f, st), "clear counters");
   std::pair<hipEvent_t, hipEvent_t>* pe = nullptr;
   if (events) {
     cg_status s = batch_event(b, &pe);
@@ -286,7 +297,7 @@ cg_status contract_part(cg_batch* b, hipStream_t st, bool events) {
   br.nranges = b->nranges.as<uint32_t>();
   br.ncand = b->ncand.as<uint64_t>();
   br.srec = reinterpret_cast<const double4*>(b->sx.as<double>());
-  CG_HIP(cg::launch_batch_mfma(dj, b->items.as<cg::BatchItem>(), b->nitems, b->counter.as<int>(),
+  CG_HIP(cg::launch_batch_mfma(dj, b->items.as<cg::BatchItem>(), b->queues, b->counter.as<int>(),
                                br, b->zrow.p, b->dtype, b->prec, b->shape, b->bpc, st),
          "batch contraction");
   if (pe) CG_HIP(hipEventRecord(pe->second, st), "event record");

@@ -1,10 +1,15 @@
 // Persistent matrix-core contraction for a batch of gridding jobs.
 //
-// Every (job, tile, channel range) of the batch is one work item; the items
-// sit in one queue ordered by estimated cost, largest first (longest
-// processing time first), and a grid sized to the resident capacity of the
-// chip takes them one at a time from an atomic counter, so jobs of very
-// different sizes share one launch without a tail of idle compute units.
+// Every (job, tile, channel range) of the batch is one work item.  The
+// items sit in one queue per XCD: each job's tiles are split into one run
+// of neighbouring tiles per XCD, and every queue lists its runs of all jobs
+// in order of estimated item cost, largest first (longest processing time
+// first).  A grid sized to the resident capacity of the chip takes items
+// one at a time from atomic counters: a workgroup drains the queue of its
+// own XCD (block b runs on XCD b % 8), so tiles that share candidate rows
+// and output lines meet in that XCD's L2, then takes what is left in the
+// other queues in turn.  Jobs of very different sizes thus share one launch
+// without a tail of idle compute units.
 // Each item runs the same tile contraction as the per-grid kernel, with the
 // kernel type (circular or elliptical) taken from the job at run time, and
 // writes the normalised cube and weights of its job directly.
@@ -20,15 +25,29 @@ namespace cg {
 // of them share a compute unit and cover each other's barrier waits)
 template <int NW, int BPW, int MODE, typename T>
 __global__ void __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) k_batch_mfma(
-    const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, int64_t nitems,
+    const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, BatchQueues q,
     int* counter, BatchRanges br, const T* __restrict__ zrow) {
-  __shared__ int s_item;
+  __shared__ int64_t s_item;
+  const int home = (int)(blockIdx.x % kNumXcd);
+  int visited = 0;   // queues found empty so far (thread 0): home, home + 1, ...
   for (;;) {
     __syncthreads();  // the previous item is done with LDS
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) {
+      int64_t next = -1;
+      while (visited < kNumXcd) {
+        const int k = (home + visited) % kNumXcd;
+        const int64_t i = atomicAdd(&counter[k], 1);
+        if (i < q.off[k + 1] - q.off[k]) {
+          next = q.off[k] + i;
+          break;
+        }
+        ++visited;   // every counter only grows, so an exhausted queue stays so
+      }
+      s_item = next;
+    }
     __syncthreads();
     const int64_t it = s_item;
-    if (it >= nitems) break;
+    if (it < 0) break;
     const BatchItem item = items[it];
     const BatchJob& jb = jobs[item.job];   // global memory, not a kernel argument
     TileView tv;
@@ -68,9 +87,10 @@ static int occ_of() {
 }
 
 template <int NW, int BPW, int MODE, typename T>
-static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
+static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, const BatchQueues& q,
                             int* counter, const BatchRanges& br, const void* zrow,
                             int blocks_per_cu, hipStream_t st) {
+  const int64_t nitems = q.off[kNumXcd];
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -82,16 +102,16 @@ static hipError_t launch_bt(const BatchJob* jobs, const BatchItem* items, int64_
   if (grid > nitems) grid = nitems;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((k_batch_mfma<NW, BPW, MODE, T>), dim3((unsigned)grid), dim3(NW * 64), 0, st,
-                     jobs, items, nitems, counter, br, (const T*)zrow);
+                     jobs, items, q, counter, br, (const T*)zrow);
   return hipGetLastError();
 }
 
 template <int MODE, typename T>
 static hipError_t launch_bs(int shape, const BatchJob* jobs, const BatchItem* items,
-                            int64_t nitems, int* counter, const BatchRanges& br,
+                            const BatchQueues& q, int* counter, const BatchRanges& br,
                             const void* zrow, int blocks_per_cu, hipStream_t st) {
 #define CG_BT(NW_, BPW_) \
-  launch_bt<NW_, BPW_, MODE, T>(jobs, items, nitems, counter, br, zrow, blocks_per_cu, st)
+  launch_bt<NW_, BPW_, MODE, T>(jobs, items, q, counter, br, zrow, blocks_per_cu, st)
   switch (shape) {
     case 0: return CG_BT(8, 1);
     case 1: return CG_BT(8, 2);
@@ -104,10 +124,10 @@ static hipError_t launch_bs(int shape, const BatchJob* jobs, const BatchItem* it
 
 template <int MODE>
 static hipError_t launch_bm(int dtype, int shape, const BatchJob* jobs, const BatchItem* items,
-                            int64_t nitems, int* counter, const BatchRanges& br,
+                            const BatchQueues& q, int* counter, const BatchRanges& br,
                             const void* zrow, int blocks_per_cu, hipStream_t st) {
 #define CG_BS(T_) \
-  launch_bs<MODE, T_>(shape, jobs, items, nitems, counter, br, zrow, blocks_per_cu, st)
+  launch_bs<MODE, T_>(shape, jobs, items, q, counter, br, zrow, blocks_per_cu, st)
   switch (dtype) {
     case 0: return CG_BS(double);
     case 1: return CG_BS(float);
@@ -117,13 +137,13 @@ static hipError_t launch_bm(int dtype, int shape, const BatchJob* jobs, const Ba
 #undef CG_BS
 }
 
-hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
+hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, const BatchQueues& q,
                              int* counter, const BatchRanges& br, const void* zrow, int dtype,
                              int prec, int shape, int blocks_per_cu, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
+  if (q.off[kNumXcd] <= 0) return hipSuccess;
   if (prec == 2)
-    return launch_bm<1>(dtype, shape, jobs, items, nitems, counter, br, zrow, blocks_per_cu, st);
-  return launch_bm<0>(dtype, shape, jobs, items, nitems, counter, br, zrow, blocks_per_cu, st);
+    return launch_bm<1>(dtype, shape, jobs, items, q, counter, br, zrow, blocks_per_cu, st);
+  return launch_bm<0>(dtype, shape, jobs, items, q, counter, br, zrow, blocks_per_cu, st);
 }
 
 template <int MODE, typename T>

@@ -186,7 +186,7 @@ __device__ __forceinline__ void work_of_block(int64_t b, int64_t ntiles, int64_t
 // together on one XCD form a compact block that shares candidate samples
 // both across and along the columns.  v is the position in the visit order.
 constexpr int64_t kStrip = 4;
-__device__ __forceinline__ int64_t strip_tile(int64_t v, int64_t ntiles, int64_t ntx) {
+__host__ __device__ __forceinline__ int64_t strip_tile(int64_t v, int64_t ntiles, int64_t ntx) {
   const int64_t nty = ntiles / ntx;
   const int64_t s = v / (kStrip * ntx);
   const int64_t h = (nty - s * kStrip) < kStrip ? (nty - s * kStrip) : kStrip;
@@ -445,11 +445,18 @@ struct BatchRanges {
   const uint64_t* ncand;
   const double4* srec;         // sorted records (rows local to each job)
 };
-// Persistent contraction over a queue of items; shape 0..3 selects the
-// workgroup (8 or 4 wavefronts, 1 or 2 channel blocks each: at most
-// batch_shape_rows(shape) channels per item); counter must be zero at launch.
+// The work queue in one segment per XCD: items [off[k], off[k + 1]) are
+// the home queue of the workgroups on XCD k (each job's tiles split into
+// kNumXcd runs of neighbouring tiles, one per XCD).
+struct BatchQueues {
+  int64_t off[kNumXcd + 1];
+};
+// Persistent contraction over the queues; shape 0..3 selects the workgroup
+// (8 or 4 wavefronts, 1 or 2 channel blocks each: at most
+// batch_shape_rows(shape) channels per item); counter holds kNumXcd ints,
+// zero at launch.
 constexpr int kBatchShapes = 4;
-hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, int64_t nitems,
+hipError_t launch_batch_mfma(const BatchJob* jobs, const BatchItem* items, const BatchQueues& q,
                              int* counter, const BatchRanges& br, const void* zrow, int dtype,
                              int prec, int shape, int blocks_per_cu, hipStream_t st);
 int batch_max_blocks_per_cu(int dtype, int prec, int shape);
