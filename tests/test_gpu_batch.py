@@ -182,3 +182,30 @@ def test_batch_replay_follows_moved_samples():
     assert b.query(4) > 2 * ncand
     for g, (lon, lat, d), (c, w) in zip(gs, ins, outs):
         _same(_out_np(c, w, g.nchan), _alone(g, lon, lat, d))
+
+
+@pytest.mark.parametrize("njobs,scale", [(6, 0.002), (2, 0.0004)])
+def test_batch_tiny_jobs_and_few_items(njobs, scale):
+    # Jobs of 1-9 tiles: each job's tiles are split into one run per XCD,
+    # so most XCD queues hold few items or none, and the second batch has
+    # fewer work items (and workgroups) than XCDs.  Every item must still be
+    # taken exactly once: each job equals the same gridder alone.
+    wls = synth.config4(njobs=njobs, scale=scale)
+    say(f"tiny batch: n={[wl.nsamples for wl in wls]} C={[wl.nchan for wl in wls]} "
+        f"grids={[wl.target['wcs']['naxis1'] for wl in wls]}")
+    b, gs, ins = _batch(wls)
+    outs = b.outputs()
+    for c, w in outs:
+        c.fill_(-7.0)
+        w.fill_(-7.0)
+    b.grid(ins, outs)
+    b.sync()
+    say(f"  items={b.query(3)}")
+    for j, (wl, g, (lon, lat, d), (cube, w)) in enumerate(zip(wls, gs, ins, outs)):
+        got = _out_np(cube, w, wl.nchan)
+        _same(got, _alone(g, lon, lat, d))
+        if j == 0:
+            ref = oracle.grid_workload(wl)
+            ev = oracle.e_val(got[0], ref["R"], ref["W"])
+            say(f"  job 0 {wl.kernel[0]} C={wl.nchan}: e_val={ev:.2e}")
+            assert ev <= TOL_MFMA
