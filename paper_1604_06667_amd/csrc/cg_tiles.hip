@@ -69,8 +69,9 @@ hipError_t launch_wcs_targets(const WcsDev& w, int64_t tile_w, int64_t tile_h, i
 }
 
 // ---------------------------------------------------------------------------
-// Sight lines: ordered along the NESTED space-filling curve so that runs of
-// 64 consecutive targets are compact tiles.
+// Sight lines: ordered along a space-filling curve (a Hilbert curve in each
+// HEALPix base face) so that runs of 64 consecutive targets are compact
+// tiles.
 
 constexpr int64_t kSlNside = 8192;
 
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(256) k_sl_keys(const double* __restrict__ lon,
     if (am < 0.0) am += 360.0;
     double sd, cd;
     sincos(d * (hpx::kPi / 180.0), &sd, &cd);
-    key = (uint32_t)hpx::ang2pix_nest(kSlNside, sd, cd, am * (hpx::kPi / 180.0));
+    key = (uint32_t)hpx::ang2hilbert(kSlNside, sd, cd, am * (hpx::kPi / 180.0));
   }
   keys[i] = key;
   vals[i] = (uint32_t)i;

@@ -373,20 +373,17 @@ CG_HD void cap_ring_span(int64_t nside, double cz, double cs, double rho,
   *last = l;
 }
 
-// Angle -> NESTED index (Gorski et al. 2005): used only to order sight-line
-// targets along a space-filling curve so that runs of consecutive targets
-// are compact.  nside must be a power of two.
-CG_HD uint64_t spread_bits(uint64_t v) {
-  v &= 0xFFFFFFFFull;
-  v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
-  v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
-  v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
-  v = (v | (v << 2)) & 0x3333333333333333ull;
-  v = (v | (v << 1)) & 0x5555555555555555ull;
-  return v;
-}
-
-CG_HD int64_t ang2pix_nest(int64_t nside, double z, double st, double phi) {
+// Ordering of sight-line targets along a space-filling curve, so that runs
+// of consecutive targets are compact.  A point's base face and in-face cell
+// (ix, iy) at a power-of-two nside follow Gorski et al. (2005), as for the
+// NESTED scheme; within the face the cells are numbered along a Hilbert
+// curve instead of the NESTED (Morton) one.  A run of a Hilbert curve is
+// always one connected piece of the face, while a Morton run jumps between
+// quadrants, so tiles of consecutive targets cover less sky and meet fewer
+// candidate samples outside their targets' supports.
+// Base face and in-face cell of a point (z = cos theta, st = sin theta).
+CG_HD void ang2xyf(int64_t nside, double z, double st, double phi, int64_t* face_out,
+                   int64_t* ix_out, int64_t* iy_out) {
   const double za = fabs(z);
   double tt = phi * (2.0 / kPi);
   if (tt >= 4.0) tt -= 4.0;
@@ -416,14 +413,47 @@ CG_HD int64_t ang2pix_nest(int64_t nside, double z, double st, double phi) {
     if (z >= 0) { face = ntt; ix = nside - jm - 1; iy = nside - jp - 1; }
     else { face = ntt + 8; ix = jp; iy = jm; }
   }
-  return face * nside * nside + (int64_t)(spread_bits((uint64_t)ix) | (spread_bits((uint64_t)iy) << 1));
+  *face_out = face;
+  *ix_out = ix;
+  *iy_out = iy;
+}
+
+// Position of cell (x, y) of an n x n grid (n a power of two) along the
+// Hilbert curve: from the top bit down, the quadrant holding the cell
+// contributes its rank along the curve, and the cell's remaining
+// coordinates are reflected or transposed into the orientation that
+// quadrant's sub-curve has.
+CG_HD uint64_t hilbert_index(int64_t n, int64_t x, int64_t y) {
+  uint64_t d = 0;
+  for (int64_t s = n / 2; s > 0; s /= 2) {
+    const int64_t rx = (x & s) != 0, ry = (y & s) != 0;
+    d += (uint64_t)s * (uint64_t)s * (uint64_t)((3 * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = n - 1 - x;
+        y = n - 1 - y;
+      }
+      const int64_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
+
+// Sight-line ordering key: face * nside^2 + Hilbert position in the face.
+CG_HD int64_t ang2hilbert(int64_t nside, double z, double st, double phi) {
+  int64_t face, ix, iy;
+  ang2xyf(nside, z, st, phi, &face, &ix, &iy);
+  return face * nside * nside + (int64_t)hilbert_index(nside, ix, iy);
 }
 
 // ---------------------------------------------------------------------------
 // Pixel centres as targets (a full HEALPix map gridded through the sight-line
 // path; the paper's App. A.1 grids onto the nside = 512 pixel centres).
 
-// Inverse of spread_bits: the even bits of v packed together.
+// The even bits of v packed together (one coordinate of a NESTED in-face
+// index, whose bits interleave the two).
 CG_HD uint64_t compact_bits(uint64_t v) {
   v &= 0x5555555555555555ull;
   v = (v | (v >> 1)) & 0x3333333333333333ull;
