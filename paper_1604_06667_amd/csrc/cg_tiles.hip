@@ -393,14 +393,28 @@ hipError_t launch_tile_windows(const double* caps, const double* txyz, int64_t n
 // slot (ring) order as (first sorted position, first candidate index of the
 // range within the tile), and the tile's candidate count is written.
 
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, uint32_t lo,
-                                                    uint32_t hi, uint64_t v) {
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if ((uint64_t)keys[mid] < v) lo = mid + 1;
-    else hi = mid;
+// First positions in keys[lo, hi) (sorted) whose key is >= v1 and >= v2:
+// the two bisections run in step, so that each step's two loads are in
+// flight together instead of one search waiting for the other.
+__device__ __forceinline__ void lower_bounds_u32(const uint32_t* __restrict__ keys, uint32_t lo,
+                                                 uint32_t hi, uint64_t v1, uint64_t v2,
+                                                 uint32_t* b, uint32_t* e) {
+  uint32_t l1 = lo, h1 = hi, l2 = lo, h2 = hi;
+  while (l1 < h1 || l2 < h2) {
+    const bool a1 = l1 < h1, a2 = l2 < h2;
+    const uint32_t m1 = l1 + ((h1 - l1) >> 1), m2 = l2 + ((h2 - l2) >> 1);
+    const uint32_t k1 = a1 ? keys[m1] : 0u, k2 = a2 ? keys[m2] : 0u;
+    if (a1) {
+      if ((uint64_t)k1 < v1) l1 = m1 + 1;
+      else h1 = m1;
+    }
+    if (a2) {
+      if ((uint64_t)k2 < v2) l2 = m2 + 1;
+      else h2 = m2;
+    }
   }
-  return lo;
+  *b = l1;
+  *e = l2;
 }
 
 __device__ __forceinline__ void tile_ranges_body(
@@ -423,8 +437,7 @@ __device__ __forceinline__ void tile_ranges_body(
       if (lo <= hi) {
         const int64_t i = f + (s >> 1);
         const uint32_t rb = ring_off[i], re = ring_off[i + 1];
-        b = lower_bound_u32(keys, rb, re, (uint64_t)lo);
-        e = lower_bound_u32(keys, b, re, (uint64_t)hi + 1);
+        lower_bounds_u32(keys, rb, re, (uint64_t)lo, (uint64_t)hi + 1, &b, &e);
       }
     }
     const bool h = e > b;
