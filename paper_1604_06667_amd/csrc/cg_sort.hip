@@ -148,27 +148,40 @@ __global__ void __launch_bounds__(kSortThreads) k_hist(const uint32_t* __restric
 }
 
 // Exclusive scan of each digit's per-block counts (one workgroup per digit,
-// coalesced), leaving the digit totals in totals[256].
+// coalesced), leaving the digit totals in totals[256].  Each pass over 1024
+// counts gives every thread four consecutive ones; the threads' sums are
+// scanned by shuffles within each wavefront and the four wavefront sums
+// are combined through LDS, one barrier per pass.
 __global__ void __launch_bounds__(256) k_digit_scan(uint32_t* __restrict__ hist, int64_t nblocks,
                                                     uint32_t* __restrict__ totals) {
-  __shared__ uint32_t s[256];
-  const int t = threadIdx.x;
+  __shared__ uint32_t s_w[2][4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   uint32_t* h = hist + (int64_t)blockIdx.x * nblocks;
   uint32_t carry = 0;
-  for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
-    const int64_t i = b0 + t;
-    const uint32_t v = i < nblocks ? h[i] : 0u;
-    s[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const uint32_t u = t >= off ? s[t - off] : 0u;
-      __syncthreads();
-      s[t] += u;
-      __syncthreads();
+  int buf = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += 1024, buf ^= 1) {
+    const int64_t i0 = b0 + 4 * (int64_t)t;
+    uint32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = i0 + q < nblocks ? h[i0 + q] : 0u;
+    const uint32_t local = v[0] + v[1] + v[2] + v[3];
+    uint32_t incl = local;   // inclusive scan of the threads' sums in the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += y;
     }
-    if (i < nblocks) h[i] = carry + s[t] - v;
-    carry += s[255];
-    __syncthreads();
+    if (lane == 63) s_w[buf][w] = incl;
+    __syncthreads();   // (double-buffered sums: the next pass writes the other half)
+    uint32_t wbase = 0;
+    for (int k = 0; k < w; ++k) wbase += s_w[buf][k];
+    uint32_t run = carry + wbase + (incl - local);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (i0 + q < nblocks) h[i0 + q] = run;
+      run += v[q];
+    }
+    carry += s_w[buf][0] + s_w[buf][1] + s_w[buf][2] + s_w[buf][3];
   }
   if (t == 0) totals[blockIdx.x] = carry;
 }
